@@ -1,0 +1,152 @@
+/*
+ * mcmg.h -- C ABI of the MI355X (gfx950) McMg solver library, libmcmg.so.
+ *
+ * McMg (arXiv 2606.30495) is a learned multi-channel multigrid
+ * preconditioner for the heterogeneous Helmholtz equation
+ *     -Lap u - k(x)^2 u = f,   k = omega / c          (Sec. 2.1, Eq. helm)
+ * discretised with the 5-point (2D) / 7-point (3D) finite-difference stencil
+ * (Eq. FDM_stencil) and a perfectly matched layer (App. A.1.1).  A setup
+ * phase turns c(x) into cached per-level features (Alg. 1); the V-cycle
+ * MG(r) ~ A^{-1} r (Sec. 3.2, Alg. 2) then preconditions a restarted,
+ * right-preconditioned flexible GMRES (Sec. 3.3: McMg as a GMRES
+ * preconditioner; Sec. 4.1: relative tolerance 1e-6, preconditioner in
+ * reduced precision, residual in FP64).
+ *
+ * Conventions shared by every entry point
+ *  - Grids: the caller gives the INTERIOR grid (n[0] x n[1] (x n[2]) nodes,
+ *    spacing h, row-major, last axis fastest).  The library adds a PML of
+ *    `pml.ncells` cells on every side; the EXTENDED grid has
+ *    n_ext[a] = n[a] + 2 * ncells nodes per axis.  Right-hand sides,
+ *    solutions and residuals live on the extended grid.
+ *  - Complex fields are interleaved complex128 (double re, double im),
+ *    row-major over the extended grid, in DEVICE memory, unless stated.
+ *  - All work is issued on the handle's stream (mcmg_opts.stream); apply and
+ *    matvec return without synchronising, solve returns when done.
+ *  - No entry point throws; every failure returns a negative mcmg_status
+ *    and mcmg_last_error() (thread-local) describes it.
+ *  - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef MCMG_H
+#define MCMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCMG_OK = 0,
+  MCMG_NOT_CONVERGED = 1,     /* maxit reached; u holds the best iterate   */
+  MCMG_E_ARG = -1,            /* invalid argument or shape                 */
+  MCMG_E_OOM = -2,            /* device allocation failed                  */
+  MCMG_E_HIP = -3,            /* a HIP runtime call failed                 */
+  MCMG_E_WEIGHTS = -4,        /* weight blob malformed or not matching     */
+  MCMG_E_NONFINITE = -5,      /* NaN/Inf in the input or the iteration     */
+  MCMG_E_BREAKDOWN = -6,      /* Krylov breakdown without convergence      */
+  MCMG_E_BUDGET = -7          /* request exceeds the server's HBM budget   */
+} mcmg_status;
+
+typedef enum { MCMG_FP32 = 0, MCMG_BF16 = 1 } mcmg_precision;
+
+typedef struct { int dim; int n[3]; } mcmg_grid;           /* interior nodes */
+
+/* PML: ncells per side; sigma_max <= 0 selects the default
+ * 3 ln(1e6) / (2 (omega / max c) ncells h) (round-trip factor 1e-6).
+ * Stretch s = 1 + i sigma_max (d / ncells)^2, d = cells into the layer. */
+typedef struct { int ncells; double sigma_max; } mcmg_pml;
+
+/* Self-describing weight blob (host memory; copied by mcmg_setup).
+ * Header: magic "MCMGWB01", version 1, dim, levels L <= 8, ksize 3,
+ * channels[8], nu1[8], nu2[8], tensor count; then a tensor table and
+ * float32 tensors [d0][d1][3^dim].  Tensor set (Sec. 3.1-3.2): f_lift,
+ * g_lift, g_proj; per level f_s, W, KA, KS, Wsm^(1..nu1+nu2) (nu1 at the
+ * coarsest level); per level l < L also f_a, R, P.  C_1 must be 2. */
+typedef struct { const void* blob; size_t bytes; } mcmg_weights;
+
+typedef struct {
+  int precision;   /* mcmg_precision of the V-cycle convolutions           */
+  int restart;     /* FGMRES restart length m (1..64; 0 selects 30)        */
+  void* stream;    /* hipStream_t for all work; NULL = default stream      */
+  int ortho;       /* 0: classical Gram-Schmidt with re-orthogonalisation
+                      when the norm drops below 1/sqrt(2) (default);
+                      1: always two passes                                 */
+} mcmg_opts;
+
+typedef struct {
+  int iters;            /* preconditioner applications (all restarts)      */
+  int restarts;         /* completed cycles                                */
+  double relres_true;   /* |f - A u|_2 / |f|_2 in FP64 at exit             */
+  double relres_est;    /* last least-squares residual estimate / |f|      */
+  int status;           /* mcmg_status of the solve                        */
+  double* hist;         /* optional host array (caller-owned): estimate
+                           |g_{j+1}| / |f| after every iteration           */
+  int hist_cap;         /* capacity of hist                                */
+  int hist_len;         /* entries written                                 */
+} mcmg_info;
+
+typedef struct mcmg_ctx* mcmg_handle;
+
+/* Setup phase (Alg. 1, once per medium).  c: HOST float64 interior wave
+ * speed (all > 0, finite).  omega > 0: angular frequency; h > 0: grid
+ * spacing.  The handle copies everything it needs (speed, PML tables,
+ * weights, per-level features a_l, s_l, V-cycle and Krylov workspace), so
+ * the caller may free its inputs on return.  Errors: E_ARG (shape, values),
+ * E_WEIGHTS (blob/dim/level mismatch, a level side < 2), E_OOM, E_HIP. */
+mcmg_status mcmg_setup(const double* c, mcmg_grid grid, double omega, double h,
+                       mcmg_pml pml, mcmg_weights w, const mcmg_opts* opt,
+                       mcmg_handle* out);
+
+/* z = MG(r): one V-cycle (Alg. 2).  r, z: device complex128 on the extended
+ * grid; may not alias.  Asynchronous on the handle's stream. */
+mcmg_status mcmg_apply(mcmg_handle h, const double* r, double* z);
+
+/* Au = A u in FP64 (Eq. FDM_stencil with the PML of App. A.1.1).  u, Au:
+ * device complex128 on the extended grid; may not alias.  Asynchronous. */
+mcmg_status mcmg_matvec(mcmg_handle h, const double* u, double* Au);
+
+/* Restarted right-preconditioned FGMRES(m) with MG as the preconditioner.
+ * f: device rhs; u: device in/out (initial guess in, solution out).  Stops
+ * when the FP64 true residual |f - A u| <= tol |f|, or after maxit
+ * preconditioner applications (returns MCMG_NOT_CONVERGED with the best u).
+ * info may be NULL.  Blocks until done. */
+mcmg_status mcmg_solve(mcmg_handle h, const double* f, double* u, double tol,
+                       int maxit, mcmg_info* info);
+
+/* Stationary McMg iteration u <- u + MG(f - A u) (Sec. 3.3,
+ * Eq. mcmg_iteration), same arguments and stopping rule as mcmg_solve. */
+mcmg_status mcmg_stationary(mcmg_handle h, const double* f, double* u,
+                            double tol, int maxit, mcmg_info* info);
+
+/* Batched FGMRES (many media and right-hand sides, uneven sizes, advanced
+ * together, one launch per operation for the whole batch).  hs[i] is the
+ * handle of problem i (the same handle may appear several times); f[i],
+ * u[i] are device arrays on that handle's extended grid.  All handles must
+ * share dim, level count, channels and precision.  Work runs on hs[0]'s
+ * stream.  infos: nb entries or NULL.  Blocks until all are done. */
+mcmg_status mcmg_solve_batch(mcmg_handle* hs, const double* const* f,
+                             double* const* u, int nb, double tol, int maxit,
+                             mcmg_info* infos);
+
+/* Extended-grid query: dim, n_ext[0..dim-1], PML cells per side. */
+mcmg_status mcmg_grid_shape(mcmg_handle h, int* dim, int n_ext[3], int* npml);
+
+/* Bytes of device memory the handle holds. */
+size_t mcmg_device_bytes(mcmg_handle h);
+
+void mcmg_destroy(mcmg_handle h);
+const char* mcmg_last_error(void);
+
+/* Test hooks: replace / read level l's (1-based) cached features a_l, s_l
+ * (device float32 [nodes][C_l], row-major nodes, channel fastest).  Used to
+ * reduce the V-cycle to a textbook multigrid with hand-set features. */
+mcmg_status mcmg_debug_set_features(mcmg_handle h, int level, const float* a,
+                                    const float* s);
+mcmg_status mcmg_debug_get_features(mcmg_handle h, int level, float* a, float* s);
+mcmg_status mcmg_debug_level_shape(mcmg_handle h, int level, int n[3], int* channels);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MCMG_H */

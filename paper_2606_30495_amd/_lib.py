@@ -1,0 +1,223 @@
+"""ctypes binding of libmcmg.so (argument marshalling only).
+
+The names mirror the C ABI in include/mcmg.h.  Device arrays are passed as
+torch tensors on the GPU (complex128 fields on the extended grid, float32
+features); PyTorch only provides device memory and streams.  Every call
+runs in the HIP library; when the library is missing the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmcmg.so")
+
+MCMG_OK = 0
+MCMG_NOT_CONVERGED = 1
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP",
+          -4: "E_WEIGHTS", -5: "E_NONFINITE", -6: "E_BREAKDOWN", -7: "E_BUDGET"}
+PRECISION = {"fp32": 0, "bf16": 1}
+
+
+class McmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3)]
+
+
+class Pml(ctypes.Structure):
+    _fields_ = [("ncells", ctypes.c_int), ("sigma_max", ctypes.c_double)]
+
+
+class Weights(ctypes.Structure):
+    _fields_ = [("blob", ctypes.c_void_p), ("bytes", ctypes.c_size_t)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int),
+                ("stream", ctypes.c_void_p), ("ortho", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("restarts", ctypes.c_int),
+                ("relres_true", ctypes.c_double), ("relres_est", ctypes.c_double),
+                ("status", ctypes.c_int), ("hist", ctypes.POINTER(ctypes.c_double)),
+                ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
+
+
+_lib = None
+
+EXPORTS = {
+    "mcmg_setup": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double), Grid, ctypes.c_double,
+                                  ctypes.c_double, Pml, Weights, ctypes.POINTER(Opts),
+                                  ctypes.POINTER(ctypes.c_void_p)]),
+    "mcmg_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mcmg_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mcmg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
+    "mcmg_stationary": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
+    "mcmg_solve_batch": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p),
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
+    "mcmg_grid_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "mcmg_device_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "mcmg_destroy": (None, [ctypes.c_void_p]),
+    "mcmg_last_error": (ctypes.c_char_p, []),
+    "mcmg_debug_set_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
+    "mcmg_debug_get_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                               ctypes.c_void_p]),
+    "mcmg_debug_level_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int),
+                                              ctypes.POINTER(ctypes.c_int)]),
+}
+
+
+def lib():
+    """Load libmcmg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_2606_30495_amd.build first")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(st):
+    if st < 0:
+        raise McmgError(st, lib().mcmg_last_error().decode())
+    return st
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Handle:
+    """One medium: setup once (Alg. 1), then apply / matvec / solve."""
+
+    def __init__(self, c, omega, h, npml, blob, precision="fp32", restart=30, sigma_max=0.0,
+                 stream=None, ortho=0):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        g = Grid(c.ndim, (ctypes.c_int * 3)(*(list(c.shape) + [1] * (3 - c.ndim))))
+        self._blob = bytes(blob)
+        w = Weights(ctypes.cast(ctypes.c_char_p(self._blob), ctypes.c_void_p), len(self._blob))
+        opts = Opts(PRECISION[precision], int(restart), _stream_ptr(stream), int(ortho))
+        out = ctypes.c_void_p()
+        _check(lib().mcmg_setup(c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), g, float(omega),
+                                float(h), Pml(int(npml), float(sigma_max)), w, ctypes.byref(opts),
+                                ctypes.byref(out)))
+        self.ptr = out
+        d = ctypes.c_int()
+        ne = (ctypes.c_int * 3)()
+        npm = ctypes.c_int()
+        _check(lib().mcmg_grid_shape(self.ptr, ctypes.byref(d), ne, ctypes.byref(npm)))
+        self.dim = d.value
+        self.ext_shape = tuple(ne[: self.dim])
+        self.npml = npm.value
+        self.restart = restart
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().mcmg_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def device_bytes(self):
+        return lib().mcmg_device_bytes(self.ptr)
+
+    def _shape_check(self, *ts):
+        import torch
+        for t in ts:
+            if t.dtype != torch.complex128 or tuple(t.shape) != self.ext_shape:
+                raise ValueError(f"expected complex128 {self.ext_shape}, got {t.dtype} {tuple(t.shape)}")
+
+    def apply(self, r, z):
+        self._shape_check(r, z)
+        _check(lib().mcmg_apply(self.ptr, _ptr(r), _ptr(z)))
+
+    def matvec(self, u, Au):
+        self._shape_check(u, Au)
+        _check(lib().mcmg_matvec(self.ptr, _ptr(u), _ptr(Au)))
+
+    def _solve(self, fn, f, u, tol, maxit, hist_cap):
+        self._shape_check(f, u)
+        hist = (ctypes.c_double * max(1, hist_cap))()
+        info = Info(0, 0, 0.0, 0.0, 0, hist, hist_cap, 0)
+        st = _check(fn(self.ptr, _ptr(f), _ptr(u), float(tol), int(maxit), ctypes.byref(info)))
+        return {"status": st, "iters": info.iters, "restarts": info.restarts,
+                "relres_true": info.relres_true, "relres_est": info.relres_est,
+                "hist": list(hist[: info.hist_len]), "converged": st == MCMG_OK}
+
+    def solve(self, f, u, tol=1e-6, maxit=500, hist_cap=4096):
+        return self._solve(lib().mcmg_solve, f, u, tol, maxit, hist_cap)
+
+    def stationary(self, f, u, tol=1e-6, maxit=500, hist_cap=4096):
+        return self._solve(lib().mcmg_stationary, f, u, tol, maxit, hist_cap)
+
+    def level_shape(self, level):
+        n = (ctypes.c_int * 3)()
+        c = ctypes.c_int()
+        _check(lib().mcmg_debug_level_shape(self.ptr, int(level), n, ctypes.byref(c)))
+        return tuple(n[: self.dim]), c.value
+
+    def set_features(self, level, a, s):
+        _check(lib().mcmg_debug_set_features(self.ptr, int(level), _ptr(a), _ptr(s)))
+
+    def get_features(self, level, a, s):
+        _check(lib().mcmg_debug_get_features(self.ptr, int(level), _ptr(a), _ptr(s)))
+
+
+def solve_batch(handles, fs, us, tol=1e-6, maxit=500, hist_cap=0):
+    nb = len(handles)
+    H = (ctypes.c_void_p * nb)(*[h.ptr.value for h in handles])
+    F = (ctypes.c_void_p * nb)(*[f.data_ptr() for f in fs])
+    U = (ctypes.c_void_p * nb)(*[u.data_ptr() for u in us])
+    for h, f, u in zip(handles, fs, us):
+        h._shape_check(f, u)
+    infos = (Info * nb)()
+    hists = []
+    for i in range(nb):
+        hb = (ctypes.c_double * max(1, hist_cap))()
+        hists.append(hb)
+        infos[i].hist = hb
+        infos[i].hist_cap = hist_cap
+    st = _check(lib().mcmg_solve_batch(H, F, U, nb, float(tol), int(maxit), infos))
+    out = []
+    for i in range(nb):
+        out.append({"status": infos[i].status, "iters": infos[i].iters,
+                    "relres_true": infos[i].relres_true, "restarts": infos[i].restarts,
+                    "hist": list(hists[i][: infos[i].hist_len]),
+                    "converged": infos[i].status == MCMG_OK})
+    return st, out

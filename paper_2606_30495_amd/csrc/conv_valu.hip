@@ -1,0 +1,178 @@
+// Direct multi-channel 3^D convolutions on the vector ALUs (float32).
+//
+// One thread computes one output node and a chunk of CT output channels;
+// blockIdx.y selects the chunk.  Weights are laid out [tap][cin][cpad] so
+// that the CT weights a thread needs for one (tap, cin) pair are contiguous
+// and wave-uniform (scalar loads).  Three sampling modes (Sec. 3.2):
+//   S1: stride 1, zero padding 1 (smoother and level operator convs, lift,
+//       projection, setup nets);
+//   S2: stride 2, pad 1, ceil(n/2) outputs (restriction R, setup f_a);
+//   T2: transposed stride-2 (prolongation P), output forced to the fine size:
+//       coarse node X feeds fine node 2X + off.
+// Epilogues fuse the elementwise work of the V-cycle into the convolution:
+//   SET / ADD (e += W * u) / MUL (s (.) (K * t)) / GELU (setup) /
+//   RESID (t = r - W * e - a (.) (KA * e), two weight tensors at once).
+#include "internal.h"
+
+namespace mcmg {
+
+namespace {
+
+__device__ __forceinline__ float load_as_f32(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ float load_as_f32(const double* p, long long i) { return (float)p[i]; }
+__device__ __forceinline__ void store_from_f32(float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void store_from_f32(double* p, long long i, float v) { p[i] = (double)v; }
+
+__device__ __forceinline__ float gelu_f(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void conv_direct(
+    const TIN* __restrict__ x, const float* __restrict__ w, const float* __restrict__ w2,
+    TOUT* __restrict__ y, const float* __restrict__ r, const float* __restrict__ feat,
+    int cin, int cout, int cpad, Dims in, Dims out) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= out.total) return;
+  const int chunk = blockIdx.y;
+  int o[3];
+  {
+    long long q = p;
+    o[2] = (int)(q % out.n[2]); q /= out.n[2];
+    o[1] = (int)(q % out.n[1]); q /= out.n[1];
+    o[0] = (int)q;
+  }
+  float acc[CT];
+  float acc2[CT];
+#pragma unroll
+  for (int k = 0; k < CT; ++k) { acc[k] = 0.f; acc2[k] = 0.f; }
+
+  constexpr int NT = (D == 2) ? 9 : 27;
+  for (int t = 0; t < NT; ++t) {
+    int off[3];
+    if (D == 2) { off[0] = t / 3 - 1; off[1] = t % 3 - 1; off[2] = 0; }
+    else { off[0] = t / 9 - 1; off[1] = (t / 3) % 3 - 1; off[2] = t % 3 - 1; }
+    int ii[3];
+    bool valid = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (a >= D) { ii[a] = 0; continue; }
+      int v;
+      if (MODE == CONV_S1) v = o[a] + off[a];
+      else if (MODE == CONV_S2) v = 2 * o[a] + off[a];
+      else {
+        const int tt = o[a] - off[a];
+        if (tt & 1) { valid = false; v = 0; }
+        else v = tt >> 1;
+      }
+      if (v < 0 || v >= in.n[a]) valid = false;
+      ii[a] = v;
+    }
+    if (!valid) continue;
+    const long long src = (((long long)ii[0] * in.n[1] + ii[1]) * in.n[2] + ii[2]) * cin;
+    const float* wt = w + (long long)t * cin * cpad + chunk * CT;
+    const float* wt2 = (EPI == EPI_RESID) ? (w2 + (long long)t * cin * cpad + chunk * CT) : nullptr;
+    for (int ci = 0; ci < cin; ++ci) {
+      const float xv = load_as_f32(x, src + ci);
+#pragma unroll
+      for (int k = 0; k < CT; ++k) acc[k] = fmaf(xv, wt[ci * cpad + k], acc[k]);
+      if (EPI == EPI_RESID) {
+#pragma unroll
+        for (int k = 0; k < CT; ++k) acc2[k] = fmaf(xv, wt2[ci * cpad + k], acc2[k]);
+      }
+    }
+  }
+  const long long dst = p * cout;
+#pragma unroll
+  for (int k = 0; k < CT; ++k) {
+    const int c = chunk * CT + k;
+    if (c >= cout) break;
+    float v = acc[k];
+    if (EPI == EPI_ADD) v = load_as_f32((const TOUT*)y, dst + c) + v;
+    else if (EPI == EPI_MUL) v = feat[dst + c] * v;
+    else if (EPI == EPI_GELU) v = gelu_f(v);
+    else if (EPI == EPI_RESID) v = r[dst + c] - v - feat[dst + c] * acc2[k];
+    store_from_f32(y, dst + c, v);
+  }
+}
+
+template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
+hipError_t run(const ConvLaunch& a, hipStream_t s) {
+  const int nchunk = (a.cout + CT - 1) / CT;
+  dim3 grid((unsigned)((a.out.total + 255) / 256), (unsigned)nchunk);
+  hipLaunchKernelGGL((conv_direct<D, CT, MODE, EPI, TIN, TOUT>), grid, dim3(256), 0, s,
+                     (const TIN*)a.x, a.w, a.w2, (TOUT*)a.y, a.r, a.feat, a.cin, a.cout,
+                     a.cpad, a.in, a.out);
+  return hipGetLastError();
+}
+
+template <int D, int CT, int MODE>
+hipError_t by_epi(const ConvLaunch& a, hipStream_t s) {
+  if (a.tin == T_F32 && a.tout == T_F32) {
+    switch (a.epi) {
+      case EPI_SET: return run<D, CT, MODE, EPI_SET, float, float>(a, s);
+      case EPI_ADD: return run<D, CT, MODE, EPI_ADD, float, float>(a, s);
+      case EPI_MUL: return run<D, CT, MODE, EPI_MUL, float, float>(a, s);
+      case EPI_GELU: return run<D, CT, MODE, EPI_GELU, float, float>(a, s);
+      case EPI_RESID: return run<D, CT, MODE, EPI_RESID, float, float>(a, s);
+    }
+  }
+  if (MODE == CONV_S1 && a.epi == EPI_SET) {
+    if (a.tin == T_F64 && a.tout == T_F32) return run<D, CT, MODE, EPI_SET, double, float>(a, s);
+    if (a.tin == T_F32 && a.tout == T_F64) return run<D, CT, MODE, EPI_SET, float, double>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, int CT>
+hipError_t by_mode(const ConvLaunch& a, hipStream_t s) {
+  switch (a.mode) {
+    case CONV_S1: return by_epi<D, CT, CONV_S1>(a, s);
+    case CONV_S2: return by_epi<D, CT, CONV_S2>(a, s);
+    case CONV_T2: return by_epi<D, CT, CONV_T2>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int conv_chunk(int cout) { return cout <= 2 ? 2 : 8; }
+
+hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
+  if (a.out.total == 0) return hipSuccess;
+  const int ct = conv_chunk(a.cout);
+  if (a.cpad % ct != 0) return hipErrorInvalidValue;
+  if (a.dim == 2) return ct == 2 ? by_mode<2, 2>(a, s) : by_mode<2, 8>(a, s);
+  if (a.dim == 3) return ct == 2 ? by_mode<3, 2>(a, s) : by_mode<3, 8>(a, s);
+  return hipErrorInvalidValue;
+}
+
+namespace {
+__global__ void zero_f32(float* p, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) p[i] = 0.f;
+}
+__global__ void zero_f64(double* p, long long n) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) p[i] = 0.0;
+}
+}  // namespace
+
+hipError_t launch_zero_f32(float* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(zero_f32, dim3((unsigned)b), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero_f64(double* p, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  long long b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  hipLaunchKernelGGL(zero_f64, dim3((unsigned)b), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace mcmg

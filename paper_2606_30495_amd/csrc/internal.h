@@ -1,0 +1,128 @@
+// Internal declarations shared by the HIP kernels and the runtime of
+// libmcmg.so.  Layouts:
+//   complex fields     : interleaved (re, im) float64 or float32, row-major
+//                        over the extended grid, last axis fastest;
+//   latent tensors     : float32 [nodes][C] (channel fastest, "NHWC");
+//   conv weights       : float32 [tap][cin][cout_pad], cout_pad a multiple
+//                        of the output-channel chunk, zero padded;
+//   PML tables         : per axis, complex float64 cm[i], cp[i] with
+//                        cm = 1/(h^2 s(i) s(i-1/2)), cp = 1/(h^2 s(i) s(i+1/2)).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace mcmg {
+
+struct Dims {
+  int n[3];            // nodes per axis (unused axes = 1)
+  long long total;     // product
+};
+
+inline Dims make_dims(int dim, const int* n) {
+  Dims d;
+  d.n[0] = n[0];
+  d.n[1] = dim > 1 ? n[1] : 1;
+  d.n[2] = dim > 2 ? n[2] : 1;
+  d.total = (long long)d.n[0] * d.n[1] * d.n[2];
+  return d;
+}
+
+enum ConvMode { CONV_S1 = 0, CONV_S2 = 1, CONV_T2 = 2 };
+enum ConvEpi {
+  EPI_SET = 0,    // y = acc
+  EPI_ADD = 1,    // y += acc
+  EPI_MUL = 2,    // y = feat * acc
+  EPI_GELU = 3,   // y = gelu(acc)
+  EPI_RESID = 4   // y = r - acc(w) - feat * acc(w2)
+};
+enum ElemType { T_F32 = 0, T_F64 = 1, T_BF16 = 2 };
+
+struct ConvLaunch {
+  int dim;
+  int mode;            // ConvMode
+  int epi;             // ConvEpi
+  int tin;             // ElemType of x
+  int tout;            // ElemType of y
+  const void* x;
+  const float* w;      // [tap][cin][cpad]
+  const float* w2;     // second tensor (EPI_RESID)
+  void* y;
+  const float* r;      // EPI_RESID residual input  [nodes_out][cout]
+  const float* feat;   // EPI_MUL / EPI_RESID feature [nodes_out][cout]
+  int cin, cout, cpad;
+  Dims in, out;
+};
+
+// Fixed output-channel chunk per thread of the VALU direct convolution.
+int conv_chunk(int cout);
+hipError_t launch_conv(const ConvLaunch& a, hipStream_t s);
+
+// Fill n floats with zero (graph-safe, no memset node).
+hipError_t launch_zero_f32(float* p, long long n, hipStream_t s);
+hipError_t launch_zero_f64(double* p, long long n, hipStream_t s);
+
+// ---- Helmholtz operator -------------------------------------------------
+struct HelmOp {
+  int dim;
+  Dims ext;
+  const double* k2;       // [nodes]
+  const double* cm[3];    // complex [n_a] (interleaved)
+  const double* cp[3];
+};
+
+// out = A u (f == nullptr) or out = f - A u; if partial != nullptr the
+// kernel writes per-block partial sums of |out|^2 (grid size returned by
+// helm_blocks()).
+int helm_blocks(const HelmOp& op);
+hipError_t launch_helm(const HelmOp& op, int tin, const void* u, const double* f,
+                       double* out, double* partial, hipStream_t s);
+
+// Setup helpers: extended k^2 and the f_lift input m = k h (float32).
+hipError_t launch_setup_medium(int dim, Dims interior, int npml, const double* c_int,
+                               double omega, double h, double* k2, float* m, hipStream_t s);
+hipError_t launch_pml_tables(int n_ext, int npml, double h, double sigma_max,
+                             double* cm, double* cp, hipStream_t s);
+
+// ---- Krylov --------------------------------------------------------------
+int red_blocks(long long n);                        // partial-sum grid size
+// partial[i * nb + b] for i < nvec: sum conj(V_i) w over block b;
+// partial[nvec * nb + b]: sum |w|^2 (complex parts interleaved).
+hipError_t launch_multidot(const double* V, long long ldv, int nvec, const double* w,
+                           long long n, double* partial, const int* skip, hipStream_t s);
+// Reduce the partials of launch_multidot: coef[i] = dot_i (complex);
+// H column j (ldh complex entries per column, column-major) gets += dot_i;
+// wnorm2[0] = |w|^2 before the pass.
+hipError_t launch_reduce_dots(const double* partial, int nb, int nvec, double* coef,
+                              double* Hcol, double* wnorm2, const int* skip, hipStream_t s);
+// w -= sum_i coef_i V_i; partial[b] = block sums of |w|^2.
+hipError_t launch_update(const double* V, long long ldv, int nvec, const double* coef,
+                         double* w, long long n, double* partial, const int* skip, hipStream_t s);
+// Norm reduce and bookkeeping for pass `pass` (0 or 1) of column j:
+// pass 0 sets hn = |w|, flags skip[0] = 1 unless |w| < eta * |w_before|
+// (or always_two); pass 1 (run only when skip[0] == 0) overwrites hn.
+hipError_t launch_reduce_norm(const double* partial, int nb, const double* wnorm2,
+                              double* hn, int* skip, int pass, int always_two,
+                              hipStream_t s);
+hipError_t launch_scale(const double* w, const double* hn, double* v, long long n,
+                        hipStream_t s);
+// Givens rotation step on column j of H (complex, column-major, ldh rows).
+// State: cs[m], sn[m] (complex), g[m+1] (complex).  Writes out[0] = |g_{j+1}|,
+// out[1] = hn, out[2] = column norm before rotation.
+hipError_t launch_givens(double* H, int ldh, int j, const double* hn, double* cs,
+                         double* sn, double* g, double* out, hipStream_t s);
+hipError_t launch_init_g(double* g, int m1, const double* beta, hipStream_t s);
+// y = H[0:k,0:k]^{-1} g[0:k] (upper triangular, complex).
+hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y,
+                            hipStream_t s);
+// u += sum_i y_i Z_i, Z float32 complex vectors with stride ldz (complex).
+hipError_t launch_zupdate(const float* Z, long long ldz, int k, const double* y, double* u,
+                          long long n, hipStream_t s);
+// out = sum of nb partials -> out[0] (and sqrt into out[1]).
+hipError_t launch_reduce_sum(const double* partial, int nb, double* out, hipStream_t s);
+// u += z (complex f64 += complex f32) -- stationary iteration.
+hipError_t launch_axpy_f32(const float* z, double* u, long long n, hipStream_t s);
+hipError_t launch_cast_f32_f64(const float* z, double* out, long long n, hipStream_t s);
+hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t s);
+
+}  // namespace mcmg

@@ -1,0 +1,369 @@
+// FP64 Arnoldi / FGMRES kernels (right-preconditioned flexible GMRES).
+//
+// Classical Gram-Schmidt in "multi-dot" form: one pass reads w once (kept in
+// registers) and every basis vector V_i once, producing all inner products
+// <V_i, w> plus |w|^2; a second pass updates w -= sum_i h_i V_i and emits
+// |w|^2.  The two-pass re-orthogonalisation runs only when the norm dropped
+// below 1/sqrt(2) of its value before the pass (the device sets a skip flag
+// that the second pass's kernels read, so the host never waits for it).
+// All reductions are fixed-order (per-block partials, then one block per
+// output), so results are bitwise reproducible run to run.
+#include "internal.h"
+
+namespace mcmg {
+
+namespace {
+
+constexpr int RB = 256;   // threads per block
+constexpr int RPT = 4;    // complex entries per thread
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Block sum, result valid in thread 0.  sh must hold RB/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < RB / 64; ++i) t += sh[i];
+  return t;
+}
+
+__global__ __launch_bounds__(RB) void multidot_kernel(const double* __restrict__ V, long long ldv,
+                                                      int nvec, const double* __restrict__ w,
+                                                      long long n, double* __restrict__ partial,
+                                                      const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  __shared__ double sh[RB / 64];
+  const int nb = gridDim.x;
+  const long long base = (long long)blockIdx.x * RB * RPT;
+  double wr[RPT], wi[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const long long p = base + (long long)q * RB + threadIdx.x;
+    if (p < n) { wr[q] = w[2 * p]; wi[q] = w[2 * p + 1]; }
+    else { wr[q] = 0.0; wi[q] = 0.0; }
+  }
+  for (int i = 0; i < nvec; ++i) {
+    const double* v = V + (long long)i * 2 * ldv;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const long long p = base + (long long)q * RB + threadIdx.x;
+      if (p < n) {
+        const double vr = v[2 * p], vi = v[2 * p + 1];
+        // conj(v) * w
+        sr += vr * wr[q] + vi * wi[q];
+        si += vr * wi[q] - vi * wr[q];
+      }
+    }
+    const double tr = block_sum(sr, sh);
+    const double ti = block_sum(si, sh);
+    if (threadIdx.x == 0) {
+      partial[2 * ((long long)i * nb + blockIdx.x)] = tr;
+      partial[2 * ((long long)i * nb + blockIdx.x) + 1] = ti;
+    }
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) s2 += wr[q] * wr[q] + wi[q] * wi[q];
+  const double t2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * ((long long)nvec * nb + blockIdx.x)] = t2;
+    partial[2 * ((long long)nvec * nb + blockIdx.x) + 1] = 0.0;
+  }
+}
+
+// One block per output: fixed-order tree reduction of nb complex partials.
+__global__ __launch_bounds__(RB) void reduce_dots_kernel(const double* __restrict__ partial, int nb,
+                                                         int nvec, double* __restrict__ coef,
+                                                         double* __restrict__ Hcol,
+                                                         double* __restrict__ wnorm2,
+                                                         const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  __shared__ double sh[RB / 64];
+  const int i = blockIdx.x;     // 0..nvec (nvec = |w|^2)
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) {
+    sr += partial[2 * ((long long)i * nb + b)];
+    si += partial[2 * ((long long)i * nb + b) + 1];
+  }
+  const double tr = block_sum(sr, sh);
+  const double ti = block_sum(si, sh);
+  if (threadIdx.x == 0) {
+    if (i < nvec) {
+      coef[2 * i] = tr;
+      coef[2 * i + 1] = ti;
+      Hcol[2 * i] += tr;
+      Hcol[2 * i + 1] += ti;
+    } else {
+      wnorm2[0] = tr;
+    }
+  }
+}
+
+__global__ __launch_bounds__(RB) void update_kernel(const double* __restrict__ V, long long ldv,
+                                                    int nvec, const double* __restrict__ coef,
+                                                    double* __restrict__ w, long long n,
+                                                    double* __restrict__ partial,
+                                                    const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  __shared__ double sh[RB / 64];
+  const long long base = (long long)blockIdx.x * RB * RPT;
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const long long p = base + (long long)q * RB + threadIdx.x;
+    if (p >= n) break;
+    double ar = w[2 * p], ai = w[2 * p + 1];
+    for (int i = 0; i < nvec; ++i) {
+      const double cr = coef[2 * i], ci = coef[2 * i + 1];
+      const double* v = V + (long long)i * 2 * ldv;
+      const double vr = v[2 * p], vi = v[2 * p + 1];
+      ar -= cr * vr - ci * vi;
+      ai -= cr * vi + ci * vr;
+    }
+    w[2 * p] = ar;
+    w[2 * p + 1] = ai;
+    s2 += ar * ar + ai * ai;
+  }
+  const double t = block_sum(s2, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(RB) void reduce_norm_kernel(const double* __restrict__ partial, int nb,
+                                                         const double* __restrict__ wnorm2,
+                                                         double* __restrict__ hn, int* skip,
+                                                         int pass, int always_two) {
+  if (pass == 1 && skip[0]) return;
+  __shared__ double sh[RB / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) s += partial[b];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(t);
+    hn[0] = nrm;
+    if (pass == 0) {
+      // eta = 1/sqrt(2): re-orthogonalise when cancellation removed more
+      // than half of |w|^2 (Daniel-Gragg-Kaufman-Stewart criterion).
+      const bool again = always_two || (nrm * nrm < 0.5 * wnorm2[0]);
+      skip[0] = again ? 0 : 1;
+    }
+  }
+}
+
+__global__ void scale_kernel(const double* __restrict__ w, const double* __restrict__ hn,
+                             double* __restrict__ v, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double inv = 1.0 / hn[0];
+  v[2 * p] = w[2 * p] * inv;
+  v[2 * p + 1] = w[2 * p + 1] * inv;
+}
+
+__global__ void init_g_kernel(double* g, int m1, const double* beta) {
+  const int i = threadIdx.x;
+  if (i < m1) {
+    g[2 * i] = (i == 0) ? beta[0] : 0.0;
+    g[2 * i + 1] = 0.0;
+  }
+}
+
+// Single-thread Givens step on column j (complex, column-major, ldh rows).
+__global__ void givens_kernel(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
+                              double* g, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + 2LL * j * ldh;
+  const double b = hn[0];
+  col[2 * (j + 1)] = b;
+  col[2 * (j + 1) + 1] = 0.0;
+  double cn = 0.0;
+  for (int i = 0; i <= j + 1; ++i) cn += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
+  cn = sqrt(cn);
+  for (int i = 0; i < j; ++i) {
+    const double xr = col[2 * i], xi = col[2 * i + 1];
+    const double yr = col[2 * (i + 1)], yi = col[2 * (i + 1) + 1];
+    const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
+    // x' = c x + conj(s) y ; y' = -s x + c y
+    col[2 * i] = c * xr + (sr * yr + si * yi);
+    col[2 * i + 1] = c * xi + (sr * yi - si * yr);
+    col[2 * (i + 1)] = -(sr * xr - si * xi) + c * yr;
+    col[2 * (i + 1) + 1] = -(sr * xi + si * xr) + c * yi;
+  }
+  const double ar = col[2 * j], ai = col[2 * j + 1];
+  const double aa = hypot(ar, ai);
+  const double t = hypot(aa, b);
+  double c, sr, si;
+  if (aa == 0.0) { c = 0.0; sr = 1.0; si = 0.0; }
+  else {
+    c = aa / t;
+    // s = (conj(a) / |a|) * (b / t)
+    sr = (ar / aa) * (b / t);
+    si = (-ai / aa) * (b / t);
+  }
+  cs[j] = c; sn[2 * j] = sr; sn[2 * j + 1] = si;
+  // new diagonal = c a + conj(s) b
+  col[2 * j] = c * ar + sr * b;
+  col[2 * j + 1] = c * ai - si * b;
+  col[2 * (j + 1)] = 0.0;
+  col[2 * (j + 1) + 1] = 0.0;
+  const double gr = g[2 * j], gi = g[2 * j + 1];
+  // g_{j+1} = -s g_j ; g_j = c g_j
+  g[2 * (j + 1)] = -(sr * gr - si * gi);
+  g[2 * (j + 1) + 1] = -(sr * gi + si * gr);
+  g[2 * j] = c * gr;
+  g[2 * j + 1] = c * gi;
+  out[0] = hypot(g[2 * (j + 1)], g[2 * (j + 1) + 1]);
+  out[1] = b;
+  out[2] = cn;
+}
+
+__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double sr = g[2 * i], si = g[2 * i + 1];
+    for (int l = i + 1; l < k; ++l) {
+      const double hr = H[2 * ((long long)l * ldh + i)], hi = H[2 * ((long long)l * ldh + i) + 1];
+      sr -= hr * y[2 * l] - hi * y[2 * l + 1];
+      si -= hr * y[2 * l + 1] + hi * y[2 * l];
+    }
+    const double dr = H[2 * ((long long)i * ldh + i)], di = H[2 * ((long long)i * ldh + i) + 1];
+    const double q = dr * dr + di * di;
+    y[2 * i] = (sr * dr + si * di) / q;
+    y[2 * i + 1] = (si * dr - sr * di) / q;
+  }
+}
+
+__global__ __launch_bounds__(RB) void zupdate_kernel(const float* __restrict__ Z, long long ldz,
+                                                     int k, const double* __restrict__ y,
+                                                     double* __restrict__ u, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double ar = u[2 * p], ai = u[2 * p + 1];
+  for (int i = 0; i < k; ++i) {
+    const float* z = Z + (long long)i * 2 * ldz;
+    const double zr = z[2 * p], zi = z[2 * p + 1];
+    const double yr = y[2 * i], yi = y[2 * i + 1];
+    ar += yr * zr - yi * zi;
+    ai += yr * zi + yi * zr;
+  }
+  u[2 * p] = ar;
+  u[2 * p + 1] = ai;
+}
+
+__global__ __launch_bounds__(RB) void reduce_sum_kernel(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[RB / 64];
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += RB) s += partial[b];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) { out[0] = t; out[1] = sqrt(t); }
+}
+
+__global__ void axpy_f32_kernel(const float* __restrict__ z, double* __restrict__ u, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * n) return;
+  u[p] += (double)z[p];
+}
+
+__global__ void cast_kernel(const float* __restrict__ z, double* __restrict__ u, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * n) return;
+  u[p] = (double)z[p];
+}
+
+__global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= 2 * n) return;
+  b[p] = a[p];
+}
+
+inline unsigned nblk(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+int red_blocks(long long n) { return (int)((n + (long long)RB * RPT - 1) / ((long long)RB * RPT)); }
+
+hipError_t launch_multidot(const double* V, long long ldv, int nvec, const double* w, long long n,
+                           double* partial, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(multidot_kernel, dim3(red_blocks(n)), dim3(RB), 0, s, V, ldv, nvec, w, n,
+                     partial, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_dots(const double* partial, int nb, int nvec, double* coef, double* Hcol,
+                              double* wnorm2, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_dots_kernel, dim3(nvec + 1), dim3(RB), 0, s, partial, nb, nvec, coef,
+                     Hcol, wnorm2, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const double* V, long long ldv, int nvec, const double* coef, double* w,
+                         long long n, double* partial, const int* skip, hipStream_t s) {
+  hipLaunchKernelGGL(update_kernel, dim3(red_blocks(n)), dim3(RB), 0, s, V, ldv, nvec, coef, w, n,
+                     partial, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_norm(const double* partial, int nb, const double* wnorm2, double* hn,
+                              int* skip, int pass, int always_two, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_norm_kernel, dim3(1), dim3(RB), 0, s, partial, nb, wnorm2, hn, skip,
+                     pass, always_two);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(const double* w, const double* hn, double* v, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_kernel, dim3(nblk(n, 256)), dim3(256), 0, s, w, hn, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_givens(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
+                         double* g, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, s, H, ldh, j, hn, cs, sn, g, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_g(double* g, int m1, const double* beta, hipStream_t s) {
+  hipLaunchKernelGGL(init_g_kernel, dim3(1), dim3(128), 0, s, g, m1, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_zupdate(const float* Z, long long ldz, int k, const double* y, double* u,
+                          long long n, hipStream_t s) {
+  hipLaunchKernelGGL(zupdate_kernel, dim3(nblk(n, RB)), dim3(RB), 0, s, Z, ldz, k, y, u, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sum(const double* partial, int nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_sum_kernel, dim3(1), dim3(RB), 0, s, partial, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32(const float* z, double* u, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_f32_kernel, dim3(nblk(2 * n, 256)), dim3(256), 0, s, z, u, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32_f64(const float* z, double* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, dim3(nblk(2 * n, 256)), dim3(256), 0, s, z, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(nblk(2 * n, 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace mcmg
