@@ -138,6 +138,16 @@ size_t mcmg_device_bytes(mcmg_handle h);
 void mcmg_destroy(mcmg_handle h);
 const char* mcmg_last_error(void);
 
+/* Per-launch timing (measurement hook).  mcmg_prof_enable(h, 1) makes the
+ * handle record a HIP event pair around every kernel launch it issues on its
+ * stream, together with the launch's algorithmic flops and bytes (from the
+ * shapes, not counters); mcmg_prof_report() synchronises, aggregates the
+ * records per kernel symbol into a JSON array of {name, launches, total_ms,
+ * avg_ms, flops_per_launch, bytes_per_launch} written to buf (host, cap
+ * bytes), and clears them.  E_ARG if buf is too small. */
+mcmg_status mcmg_prof_enable(mcmg_handle h, int on);
+mcmg_status mcmg_prof_report(mcmg_handle h, char* buf, size_t cap);
+
 /* Test hooks: replace / read level l's (1-based) cached features a_l, s_l
  * (device float32 [nodes][C_l], row-major nodes, channel fastest).  Used to
  * reduce the V-cycle to a textbook multigrid with hand-set features. */

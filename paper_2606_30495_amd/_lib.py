@@ -71,6 +71,8 @@ EXPORTS = {
     "mcmg_device_bytes": (ctypes.c_size_t, [ctypes.c_void_p]),
     "mcmg_destroy": (None, [ctypes.c_void_p]),
     "mcmg_last_error": (ctypes.c_char_p, []),
+    "mcmg_prof_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "mcmg_prof_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
     "mcmg_debug_set_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                                ctypes.c_void_p]),
     "mcmg_debug_get_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -185,6 +187,15 @@ class Handle:
 
     def stationary(self, f, u, tol=1e-6, maxit=500, hist_cap=4096):
         return self._solve(lib().mcmg_stationary, f, u, tol, maxit, hist_cap)
+
+    def prof_enable(self, on=True):
+        _check(lib().mcmg_prof_enable(self.ptr, 1 if on else 0))
+
+    def prof_report(self):
+        import json
+        buf = ctypes.create_string_buffer(1 << 20)
+        _check(lib().mcmg_prof_report(self.ptr, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def level_shape(self, level):
         n = (ctypes.c_int * 3)()

@@ -1,0 +1,30 @@
+// Implicit-GEMM convolutions on the matrix cores (see conv_mfma.hip).
+#pragma once
+#include "internal.h"
+
+namespace mcmg {
+
+struct MfmaConv {
+  int dim;
+  int bf16;              // 1: bf16 operands, 0: float32 operands (float32 accumulate)
+  int mode;              // CONV_S1 / CONV_S2 (restriction) / CONV_T2 (prolongation)
+  int epi;               // EPI_SET / EPI_ADD / EPI_MUL / EPI_RESID
+  int mt, ntw;           // tile: 16*mt output nodes per wave row, ntw column tiles per block
+  const float* x;        // input [in nodes][cin] float32
+  const void* wA;        // packed [4*nsteps][ncols][KV] (bf16 or float32)
+  const void* wB;        // second packed tensor (EPI_RESID)
+  float* y;              // output [out nodes][cout]
+  const float* r;        // EPI_RESID
+  const float* feat;     // EPI_MUL / EPI_RESID
+  int cin, cinp, cout, ncols, nsteps, npairs;
+  Dims in, out;
+};
+
+// Padded sizes of the packed operands (see conv_mfma.hip for the layout).
+void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
+                    int* npairs, int* nsteps);
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi);
+hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s);
+const char* mfma_kernel_name(const MfmaConv& a);
+
+}  // namespace mcmg

@@ -1,0 +1,345 @@
+// Multi-channel 3^D convolutions of the V-cycle as implicit GEMMs on the
+// gfx950 matrix cores (smoother / level-operator convolutions, restriction R
+// and prolongation P of Sec. 3.2).
+//
+// GEMM view: rows = output nodes, columns = output channels, K = (tap,
+// input channel).  K is enumerated in "pairs" q = tap * (cinp/KV) + cb, a
+// vector of KV consecutive input channels of one tap, so small channel
+// counts do not pad K per tap; one MFMA K-step takes 4 pairs (one per group
+// of 16 lanes):
+//   float32: v_mfma_f32_16x16x4f32     (KV = 1)
+//   bf16   : v_mfma_f32_16x16x32_bf16  (KV = 8), float32 accumulation.
+// Lane layout of the 16x16 tiles: lane l holds A[row l%16][k-group l/16] and
+// B[k-group l/16][col l%16]; the accumulator holds D[4 (l/16) + r][l%16].
+//
+// Modes (sampling of the A operand):
+//   S1: stride 1, zero padding 1 (3^D taps);
+//   S2: restriction, coarse node X reads fine nodes 2X + off (3^D taps);
+//   T2: prolongation as a depth-to-space convolution on the coarse grid:
+//       fine node 2X + a (a in {0,1}^D) only sees coarse nodes X + w,
+//       w in {0,1}^D, through tap d = a - 2w + 1 of P; so a 2^D-window
+//       convolution producing 2^D * C_fine columns (column = a * C_fine + c)
+//       followed by a scatter to the fine grid is exactly the transposed
+//       convolution with its output cropped to the fine size.
+//
+// A workgroup (4 waves) owns 4 output rows (2D) or 2 x 2 rows (3D) of
+// 16 * MT nodes and NTW column tiles (blockIdx.y selects the column slice).
+// The input tile (with halo) is staged once in LDS (zero outside the grid and
+// in padded channels; bf16 with round-to-nearest-even in the bf16 form); the
+// weights stream through LDS in chunks of KS K-steps.  Tiles are ordered so
+// that each XCD (blockIdx % 8) walks a contiguous band of the grid.
+//
+// Epilogues (state stays float32): SET y = acc; ADD y += acc; MUL y = feat *
+// acc; RESID y = r - acc(W) - feat * acc(KA).
+#include <string>
+#include <type_traits>
+
+#include "conv_mfma.h"
+#include "internal.h"
+
+namespace mcmg {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+__device__ __forceinline__ u16 f2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (u16)(u >> 16);
+}
+
+// Output tile and staged input tile geometry per (D, MODE, MT).
+template <int D, int MODE, int MT>
+struct Geo {
+  static constexpr int TX = 16 * MT;
+  static constexpr int TY = (D == 2) ? 4 : 2;
+  static constexpr int TZ = (D == 2) ? 1 : 2;
+  // staged tile extent per axis
+  static constexpr int ext(int t) { return MODE == CONV_S1 ? t + 2 : (MODE == CONV_S2 ? 2 * t + 1 : t + 1); }
+  static constexpr int HX = ext(TX), HY = ext(TY), HZ = (D == 2) ? 1 : ext(TZ);
+  static constexpr int NODES = HX * HY * HZ;
+  static constexpr int TAPS = (MODE == CONV_T2) ? ((D == 2) ? 4 : 8) : ((D == 2) ? 9 : 27);
+  static constexpr int W = (MODE == CONV_T2) ? 2 : 3;   // window per axis
+};
+
+template <bool BF> constexpr int KVOF() { return BF ? 8 : 1; }
+template <bool BF> constexpr int KSOF() { return BF ? 6 : 24; }   // K-steps per weight chunk
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
+__global__ __launch_bounds__(256) void mconv_kernel(
+    const float* __restrict__ x, const void* __restrict__ wA, const void* __restrict__ wB,
+    float* __restrict__ y, const float* __restrict__ r, const float* __restrict__ feat, int cin,
+    int cinp, int cout, int ncols, int nsteps, int npairs, Dims in, Dims out, int tiles_x,
+    int tiles_y, int tiles_z) {
+  using G = Geo<D, MODE, MT>;
+  constexpr int KV = KVOF<BF>();
+  constexpr int KS = KSOF<BF>();
+  constexpr int NACC = (EPI == EPI_RESID) ? 2 : 1;
+  constexpr int ES = BF ? 2 : 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int stride = cinp + (BF ? 8 : 1);  // LDS node stride (elements)
+  unsigned char* bsm = smem + (((size_t)G::NODES * stride * ES + 15) / 16) * 16;
+  constexpr int BROW = NTW * 16 * KV;      // elements of one pair row in the chunk
+
+  const int ntiles = tiles_x * tiles_y * tiles_z;
+  const int per = (ntiles + 7) / 8;
+  const int tl = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tl >= ntiles) return;
+  const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, tz = tl / (tiles_x * tiles_y);
+  const int x0 = tx * G::TX, y0 = ty * G::TY, z0 = tz * G::TZ;
+  const int col0 = blockIdx.y * NTW * 16;
+  // grids: 2D (n[0] rows, n[1] x), 3D (n[0] z, n[1] y, n[2] x)
+  const int IX = (D == 2) ? in.n[1] : in.n[2], IY = (D == 2) ? in.n[0] : in.n[1];
+  const int IZ = (D == 2) ? 1 : in.n[0];
+  const int OX = (D == 2) ? out.n[1] : out.n[2], OY = (D == 2) ? out.n[0] : out.n[1];
+  const int OZ = (D == 2) ? 1 : out.n[0];
+  // origin of the staged tile in input coordinates
+  int sx, sy, sz;
+  if (MODE == CONV_S1) { sx = x0 - 1; sy = y0 - 1; sz = z0 - 1; }
+  else if (MODE == CONV_S2) { sx = 2 * x0 - 1; sy = 2 * y0 - 1; sz = 2 * z0 - 1; }
+  else { sx = x0; sy = y0; sz = z0; }
+  if (D == 2) sz = 0;
+
+  // ---- stage the input tile
+  {
+    const bool vec4 = (cin % 4) == 0;
+    const int ng = cinp / 4;
+    for (int idx = threadIdx.x; idx < G::NODES * ng; idx += 256) {
+      const int node = idx / ng, c = (idx % ng) * 4;
+      const int hx = node % G::HX, hy = (node / G::HX) % G::HY, hz = node / (G::HX * G::HY);
+      const int gx = sx + hx, gy = sy + hy, gz = sz + hz;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (gx >= 0 && gx < IX && gy >= 0 && gy < IY && gz >= 0 && gz < IZ) {
+        const long long g = (((long long)gz * IY + gy) * IX + gx) * cin;
+        if (vec4) {
+          if (c < cin) {
+            const float4 t = *reinterpret_cast<const float4*>(x + g + c);
+            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (c + k < cin) v[k] = x[g + c + k];
+        }
+      }
+      if constexpr (BF) {
+        u16* s = reinterpret_cast<u16*>(smem) + (size_t)node * stride + c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = f2bf(v[k]);
+      } else {
+        float* s = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] = v[k];
+      }
+    }
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int wy = (D == 2) ? wave : (wave & 1);
+  const int wz = (D == 2) ? 0 : (wave >> 1);
+
+  floatx4 acc[NACC][MT][NTW];
+#pragma unroll
+  for (int a = 0; a < NACC; ++a)
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) acc[a][m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int cpv = cinp / KV;
+  for (int s0 = 0; s0 < nsteps; s0 += KS) {
+    const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
+    __syncthreads();   // previous chunk consumed (and input tile staged)
+    {
+      // weight chunk rows q in [4 s0, 4 (s0 + ks)), columns [col0, col0 + 16 NTW)
+      const int nrow = 4 * ks;
+      constexpr int V16 = BROW * ES / 16;    // 16-byte vectors per row
+      for (int idx = threadIdx.x; idx < NACC * nrow * V16; idx += 256) {
+        const int a = idx / (nrow * V16);
+        const int rem = idx % (nrow * V16);
+        const int row = rem / V16, v = rem % V16;
+        const unsigned char* src = reinterpret_cast<const unsigned char*>(a ? wB : wA) +
+                                   (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)v * 16;
+        unsigned char* dst = bsm + (((size_t)a * 4 * KS + row) * BROW) * ES + (size_t)v * 16;
+        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ss = 0; ss < ks; ++ss) {
+      const int s = s0 + ss;
+      int q = 4 * s + lg;
+      if (q >= npairs) q = npairs - 1;   // weight rows are zero there
+      const int tap = q / cpv, cb = q - tap * cpv;
+      int dz = 0, dy, dx;
+      if (D == 2) { dy = tap / G::W; dx = tap % G::W; }
+      else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
+      typename std::conditional<BF, bf16x8, float>::type bf[NACC][NTW];
+#pragma unroll
+      for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+          const size_t o = ((size_t)a * 4 * KS + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
+          if constexpr (BF) bf[a][t] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(bsm) + o);
+          else bf[a][t] = reinterpret_cast<const float*>(bsm)[o];
+        }
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int ox = m * 16 + li;   // output x inside the tile
+        int hx, hy, hz;
+        if (MODE == CONV_S2) { hx = 2 * ox + dx; hy = 2 * wy + dy; hz = 2 * wz + dz; }
+        else { hx = ox + dx; hy = wy + dy; hz = wz + dz; }
+        const size_t node = ((size_t)hz * G::HY + hy) * G::HX + hx;
+        if constexpr (BF) {
+          const bf16x8 af = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) +
+                                                             node * stride + cb * KV);
+#pragma unroll
+          for (int t = 0; t < NTW; ++t)
+#pragma unroll
+            for (int a = 0; a < NACC; ++a)
+              acc[a][m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[a][t], acc[a][m][t], 0, 0, 0);
+        } else {
+          const float af = reinterpret_cast<const float*>(smem)[node * stride + cb];
+#pragma unroll
+          for (int t = 0; t < NTW; ++t)
+#pragma unroll
+            for (int a = 0; a < NACC; ++a)
+              acc[a][m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[a][t], acc[a][m][t], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // ---- epilogue
+  const int gy = y0 + wy, gz = z0 + wz;
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+      const int col = col0 + t * 16 + li;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int gx = x0 + m * 16 + 4 * lg + rr;
+        long long o;
+        if (MODE == CONV_T2) {
+          // column = class * cout + c; class bits: x fastest
+          const int cls = col / cout, c = col - cls * cout;
+          if (cls >= (1 << D)) continue;
+          const int ax = cls & 1, ay = (cls >> 1) & 1, az = (D == 3) ? ((cls >> 2) & 1) : 0;
+          const int fx = 2 * gx + ax, fy = 2 * gy + ay, fz = (D == 3) ? 2 * gz + az : 0;
+          if (fx >= OX || fy >= OY || fz >= OZ) continue;
+          o = (((long long)fz * OY + fy) * OX + fx) * cout + c;
+        } else {
+          if (col >= cout || gx >= OX || gy >= OY || gz >= OZ) continue;
+          o = (((long long)gz * OY + gy) * OX + gx) * cout + col;
+        }
+        float v = acc[0][m][t][rr];
+        if (EPI == EPI_ADD) v = y[o] + v;
+        else if (EPI == EPI_MUL) v = feat[o] * v;
+        else if (EPI == EPI_RESID) v = r[o] - v - feat[o] * acc[NACC - 1][m][t][rr];
+        y[o] = v;
+      }
+    }
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
+hipError_t run(const MfmaConv& a, hipStream_t s) {
+  using G = Geo<D, MODE, MT>;
+  // output tiles are taken over the GEMM row grid: S1 = output grid,
+  // S2 = coarse output grid, T2 = coarse (input) grid
+  const Dims& rows = (MODE == CONV_T2) ? a.in : a.out;
+  const int RX = (D == 2) ? rows.n[1] : rows.n[2], RY = (D == 2) ? rows.n[0] : rows.n[1];
+  const int RZ = (D == 2) ? 1 : rows.n[0];
+  const int tx = (RX + G::TX - 1) / G::TX, ty = (RY + G::TY - 1) / G::TY, tz = (RZ + G::TZ - 1) / G::TZ;
+  const int ntiles = tx * ty * tz;
+  const int nblk = ((ntiles + 7) / 8) * 8;
+  const int nslices = a.ncols / (16 * NTW);
+  hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW>), dim3(nblk, nslices), dim3(256),
+                     mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi), s, a.x, a.wA,
+                     a.wB, a.y, a.r, a.feat, a.cin, a.cinp, a.cout, a.ncols, a.nsteps, a.npairs, a.in,
+                     a.out, tx, ty, tz);
+  return hipGetLastError();
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT>
+hipError_t by_ntw(const MfmaConv& a, hipStream_t s) {
+  switch (a.ntw) {
+    case 1: return run<D, BF, MODE, EPI, MT, 1>(a, s);
+    case 2: return run<D, BF, MODE, EPI, MT, 2>(a, s);
+    case 4: return run<D, BF, MODE, EPI, MT, 4>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF, int MODE, int EPI>
+hipError_t by_mt(const MfmaConv& a, hipStream_t s) {
+  switch (a.mt) {
+    case 1: return by_ntw<D, BF, MODE, EPI, 1>(a, s);
+    case 2: return by_ntw<D, BF, MODE, EPI, 2>(a, s);
+    case 4: return by_ntw<D, BF, MODE, EPI, 4>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF>
+hipError_t by_mode(const MfmaConv& a, hipStream_t s) {
+  if (a.mode == CONV_S1) {
+    switch (a.epi) {
+      case EPI_SET: return by_mt<D, BF, CONV_S1, EPI_SET>(a, s);
+      case EPI_ADD: return by_mt<D, BF, CONV_S1, EPI_ADD>(a, s);
+      case EPI_MUL: return by_mt<D, BF, CONV_S1, EPI_MUL>(a, s);
+      case EPI_RESID: return by_mt<D, BF, CONV_S1, EPI_RESID>(a, s);
+    }
+  } else if (a.mode == CONV_S2 && a.epi == EPI_SET) {
+    return by_mt<D, BF, CONV_S2, EPI_SET>(a, s);
+  } else if (a.mode == CONV_T2 && a.epi == EPI_ADD) {
+    return by_mt<D, BF, CONV_T2, EPI_ADD>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi) {
+  const int TX = 16 * mt, TY = dim == 2 ? 4 : 2, TZ = dim == 2 ? 1 : 2;
+  auto ext = [&](int t) { return mode == CONV_S1 ? t + 2 : (mode == CONV_S2 ? 2 * t + 1 : t + 1); };
+  const size_t nodes = (size_t)ext(TX) * ext(TY) * (dim == 2 ? 1 : ext(TZ));
+  const int es = bf16 ? 2 : 4, kv = bf16 ? 8 : 1, ks = bf16 ? 6 : 24;
+  const size_t stride = cinp + (bf16 ? 8 : 1);
+  const size_t a = ((nodes * stride * es + 15) / 16) * 16;
+  const size_t b = (size_t)(epi == EPI_RESID ? 2 : 1) * 4 * ks * ntw * 16 * kv * es;
+  return a + b;
+}
+
+void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
+                    int* npairs, int* nsteps) {
+  const int KV = bf16 ? 8 : 1;
+  const int T = mode == CONV_T2 ? (dim == 2 ? 4 : 8) : (dim == 2 ? 9 : 27);
+  *cinp = (cin + KV - 1) / KV * KV;
+  if (*cinp % 4) *cinp = (*cinp + 3) / 4 * 4;     // staging works in groups of 4
+  const int cols = mode == CONV_T2 ? (1 << dim) * cout : cout;
+  *ncols = (cols + 15) / 16 * 16;
+  *npairs = T * (*cinp / KV);
+  *nsteps = (*npairs + 3) / 4;
+}
+
+hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s) {
+  if (a.out.total == 0 || a.in.total == 0) return hipSuccess;
+  if (a.dim == 2) return a.bf16 ? by_mode<2, true>(a, s) : by_mode<2, false>(a, s);
+  if (a.dim == 3) return a.bf16 ? by_mode<3, true>(a, s) : by_mode<3, false>(a, s);
+  return hipErrorInvalidValue;
+}
+
+const char* mfma_kernel_name(const MfmaConv& a) {
+  static const char* mode_s[3] = {"S1", "S2", "T2"};
+  static const char* epi_s[5] = {"SET", "ADD", "MUL", "GELU", "RESID"};
+  return intern_name(std::string("mconv_kernel<") + std::to_string(a.dim) + "," +
+                     (a.bf16 ? "bf16" : "f32") + "," + mode_s[a.mode] + "," + epi_s[a.epi] + "," +
+                     std::to_string(a.mt) + "," + std::to_string(a.ntw) + ">");
+}
+
+}  // namespace mcmg

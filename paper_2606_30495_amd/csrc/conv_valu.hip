@@ -12,6 +12,8 @@
 // Epilogues fuse the elementwise work of the V-cycle into the convolution:
 //   SET / ADD (e += W * u) / MUL (s (.) (K * t)) / GELU (setup) /
 //   RESID (t = r - W * e - a (.) (KA * e), two weight tensors at once).
+#include <string>
+
 #include "internal.h"
 
 namespace mcmg {
@@ -173,6 +175,33 @@ hipError_t launch_zero_f64(double* p, long long n, hipStream_t s) {
   if (b > 65536) b = 65536;
   hipLaunchKernelGGL(zero_f64, dim3((unsigned)b), dim3(256), 0, s, p, n);
   return hipGetLastError();
+}
+
+}  // namespace mcmg
+
+namespace mcmg {
+
+const char* conv_kernel_name(const ConvLaunch& a) {
+  static const char* mode_s[3] = {"S1", "S2", "T2"};
+  static const char* epi_s[5] = {"SET", "ADD", "MUL", "GELU", "RESID"};
+  static const char* ty_s[3] = {"f32", "f64", "bf16"};
+  const int ct = conv_chunk(a.cout);
+  return intern_name(std::string("conv_direct<") + std::to_string(a.dim) + "," +
+                     std::to_string(ct) + "," + mode_s[a.mode] + "," + epi_s[a.epi] + "," +
+                     ty_s[a.tin] + "," + ty_s[a.tout] + ">");
+}
+
+void conv_work(const ConvLaunch& a, double* flops, double* bytes) {
+  const double T = a.dim == 2 ? 9.0 : 27.0;
+  const double pin = (double)a.in.total, pout = (double)a.out.total;
+  const double macs = T * a.cin * a.cout * (a.mode == CONV_T2 ? pin : pout);
+  *flops = 2.0 * macs * (a.epi == EPI_RESID ? 2.0 : 1.0);
+  const double szin = a.tin == T_F64 ? 8.0 : (a.tin == T_BF16 ? 2.0 : 4.0);
+  const double szout = a.tout == T_F64 ? 8.0 : (a.tout == T_BF16 ? 2.0 : 4.0);
+  double b = pin * a.cin * szin + pout * a.cout * szout;
+  if (a.epi == EPI_ADD || a.epi == EPI_MUL) b += pout * a.cout * 4.0;
+  if (a.epi == EPI_RESID) b += 2.0 * pout * a.cout * 4.0;
+  *bytes = b;
 }
 
 }  // namespace mcmg

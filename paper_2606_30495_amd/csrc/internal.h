@@ -54,6 +54,16 @@ struct ConvLaunch {
   Dims in, out;
 };
 
+// Stable C string for a kernel name (interned for the process lifetime).
+}  // namespace mcmg
+#include <string>
+namespace mcmg {
+const char* intern_name(const std::string& s);
+// Kernel symbol of a convolution launch (for per-launch timing records).
+const char* conv_kernel_name(const ConvLaunch& a);
+// Algorithmic work of a convolution launch.
+void conv_work(const ConvLaunch& a, double* flops, double* bytes);
+
 // Fixed output-channel chunk per thread of the VALU direct convolution.
 int conv_chunk(int cout);
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s);
@@ -125,4 +135,24 @@ hipError_t launch_axpy_f32(const float* z, double* u, long long n, hipStream_t s
 hipError_t launch_cast_f32_f64(const float* z, double* out, long long n, hipStream_t s);
 hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t s);
 
+}  // namespace mcmg
+
+namespace mcmg {
+// ---- fused finest-level (C = 2) smoothing step -----------------------------
+struct L1Weights {            // [cout][cin][tap] of the level-1 tensors
+  float W[2][2][27];
+  float KA[2][2][27];
+  float KS[2][2][27];
+  float Wsm[2][2][27];
+};
+enum { L1_STEP = 0, L1_FIRST = 1, L1_RESID = 2 };
+struct L1Launch {
+  int dim, var;
+  const float* e;             // current correction [nodes][2] (unused for FIRST)
+  float* eo;                  // updated correction (RESID: t = r - A e)
+  const float *r, *a, *s;
+  L1Weights w;
+  Dims n;
+};
+hipError_t launch_level1(const L1Launch& l, hipStream_t s);
 }  // namespace mcmg

@@ -6,12 +6,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
 #include "internal.h"
 #include "mcmg.h"
 #include "runtime.h"
+#include "conv_mfma.h"
 
 using namespace mcmg;
 
@@ -20,6 +24,13 @@ thread_local std::string g_err;
 }
 
 namespace mcmg {
+
+const char* intern_name(const std::string& s) {
+  static std::mutex mu;
+  static std::set<std::string> names;
+  std::lock_guard<std::mutex> lk(mu);
+  return names.insert(s).first->c_str();
+}
 
 mcmg_status fail(mcmg_status s, const char* fmt, ...) {
   char buf[512];
@@ -203,7 +214,12 @@ hipError_t Ctx::conv(int mode, int epi, int tin, const void* x, const Dims& in, 
   return dispatch_conv(a);
 }
 
-hipError_t Ctx::dispatch_conv(const ConvLaunch& a) { return launch_conv(a, stream); }
+hipError_t Ctx::dispatch_conv(const ConvLaunch& a) {
+  if (!prof.on) return launch_conv(a, stream);
+  double fl, by;
+  conv_work(a, &fl, &by);
+  return timed(conv_kernel_name(a), fl, by, [&] { return launch_conv(a, stream); });
+}
 
 // Alg. 2.  rin: complex field (tin = T_F64 or T_F32); zout: complex (tout).
 hipError_t Ctx::vcycle(const void* rin, int tin, void* zout, int tout) {
@@ -221,18 +237,26 @@ hipError_t Ctx::vcycle(const void* rin, int tin, void* zout, int tout) {
     if (l < L - 1) {
       Level& nx = lev[l + 1];
       // t = r - A e ; r_{l+1} = R * t
-      CK(conv(CONV_S1, EPI_RESID, T_F32, lv.e, lv.dims, lv.C, lv.w_W, lv.w_KA, T_F32, lv.t,
-              lv.dims, lv.C, lv.r, lv.a));
-      CK(conv(CONV_S2, EPI_SET, T_F32, lv.t, lv.dims, lv.C, lv.w_R, nullptr, T_F32, nx.r, nx.dims,
-              nx.C, nullptr, nullptr));
+      if (!lv.l1w.empty())
+        CK(level1(lv, L1_RESID, 0));
+      else
+        CK(conv_level(lv, EPI_RESID, lv.e, lv.w_W, lv.m_W, lv.w_KA, lv.m_KA, lv.t, lv.r, lv.a));
+      if (lv.op_R.on)
+        CK(run_mop(lv.op_R, lv.t, lv.m_R, nullptr, nx.r, nullptr, nullptr));
+      else
+        CK(conv(CONV_S2, EPI_SET, T_F32, lv.t, lv.dims, lv.C, lv.w_R, nullptr, T_F32, nx.r, nx.dims,
+                nx.C, nullptr, nullptr));
     }
   }
   // up cycle
   for (int l = L - 2; l >= 0; --l) {
     Level& lv = lev[l];
     Level& nx = lev[l + 1];
-    CK(conv(CONV_T2, EPI_ADD, T_F32, nx.e, nx.dims, nx.C, lv.w_P, nullptr, T_F32, lv.e, lv.dims,
-            lv.C, nullptr, nullptr));
+    if (lv.op_P.on)
+      CK(run_mop(lv.op_P, nx.e, lv.m_P, nullptr, lv.e, nullptr, nullptr));
+    else
+      CK(conv(CONV_T2, EPI_ADD, T_F32, nx.e, nx.dims, nx.C, lv.w_P, nullptr, T_F32, lv.e, lv.dims,
+              lv.C, nullptr, nullptr));
     for (int i = 0; i < lv.nu2; ++i) CK(smooth_step(lv, lv.nu1 + i, false));
   }
   // projection
@@ -244,19 +268,78 @@ hipError_t Ctx::vcycle(const void* rin, int tin, void* zout, int tout) {
 
 // e <- e + Wsm^(i) * (s (.) (KS * (r - A e))); `first` means e == 0.
 hipError_t Ctx::smooth_step(Level& lv, int i, bool first) {
+  if (!lv.l1w.empty()) return level1(lv, first ? L1_FIRST : L1_STEP, i);
   hipError_t e;
   const float* tin = lv.r;
   if (!first) {
-    e = conv(CONV_S1, EPI_RESID, T_F32, lv.e, lv.dims, lv.C, lv.w_W, lv.w_KA, T_F32, lv.t, lv.dims,
-             lv.C, lv.r, lv.a);
+    e = conv_level(lv, EPI_RESID, lv.e, lv.w_W, lv.m_W, lv.w_KA, lv.m_KA, lv.t, lv.r, lv.a);
     if (e != hipSuccess) return e;
     tin = lv.t;
   }
-  e = conv(CONV_S1, EPI_MUL, T_F32, tin, lv.dims, lv.C, lv.w_KS, nullptr, T_F32, lv.u, lv.dims,
-           lv.C, nullptr, lv.s);
+  e = conv_level(lv, EPI_MUL, tin, lv.w_KS, lv.m_KS, nullptr, nullptr, lv.u, nullptr, lv.s);
   if (e != hipSuccess) return e;
-  return conv(CONV_S1, first ? EPI_SET : EPI_ADD, T_F32, lv.u, lv.dims, lv.C, lv.w_sm[i], nullptr,
-              T_F32, lv.e, lv.dims, lv.C, nullptr, nullptr);
+  return conv_level(lv, first ? EPI_SET : EPI_ADD, lv.u, lv.w_sm[i],
+                    lv.m_sm.empty() ? nullptr : lv.m_sm[i], nullptr, nullptr, lv.e, nullptr, nullptr);
+}
+
+// Fused C = 2 sweep: STEP / FIRST write the new e into e_alt and swap the
+// two buffers; RESID writes t = r - A e into lv.t.
+hipError_t Ctx::level1(Level& lv, int var, int step) {
+  L1Launch l;
+  l.dim = dim;
+  l.var = var;
+  l.e = lv.e;
+  l.eo = var == L1_RESID ? lv.t : lv.e_alt;
+  l.r = lv.r; l.a = lv.a; l.s = lv.s;
+  l.w = lv.l1w[var == L1_RESID ? 0 : step];
+  l.n = lv.dims;
+  hipError_t e;
+  if (!prof.on) {
+    e = launch_level1(l, stream);
+  } else {
+    const double P = (double)lv.dims.total, T = dim == 2 ? 9.0 : 27.0;
+    const double fl = var == L1_RESID ? 2.0 * T * 4 * 2 * P : 2.0 * T * 4 * (var == L1_FIRST ? 2 : 4) * P;
+    const double by = var == L1_RESID ? 32.0 * P : (var == L1_FIRST ? 24.0 * P : 40.0 * P);
+    static const char* nm[3] = {"l1_kernel<STEP>", "l1_kernel<FIRST>", "l1_kernel<RESID>"};
+    const char* name = intern_name(std::string(nm[var]) + (dim == 2 ? "2d" : "3d"));
+    e = timed(name, fl, by, [&] { return launch_level1(l, stream); });
+  }
+  if (e == hipSuccess && var != L1_RESID) std::swap(lv.e, lv.e_alt);
+  return e;
+}
+
+mcmg_status Ctx::plan_level1() {
+  for (int l = 0; l < L; ++l) {
+    Level& lv = lev[l];
+    if (lv.C != 2) continue;
+    const int T = dim == 2 ? 9 : 27;
+    auto find = [&](int kind, int step) -> const std::vector<float>* {
+      for (const HostTensor& t : host_w)
+        if (t.kind == kind && t.level == l + 1 && t.step == step) return &t.w;
+      return nullptr;
+    };
+    const std::vector<float>*W = find(4, 0), *KA = find(5, 0), *KS = find(6, 0);
+    if (!W || !KA || !KS) return fail(MCMG_E_WEIGHTS, "missing level tensors");
+    auto fill = [&](float (*dst)[2][27], const std::vector<float>& src) {
+      for (int o = 0; o < 2; ++o)
+        for (int c = 0; c < 2; ++c)
+          for (int t = 0; t < 27; ++t) dst[o][c][t] = t < T ? src[((size_t)o * 2 + c) * T + t] : 0.f;
+    };
+    const int nsteps = (int)lv.w_sm.size();
+    lv.l1w.assign(nsteps > 0 ? nsteps : 1, L1Weights());
+    for (int i = 0; i < (int)lv.l1w.size(); ++i) {
+      L1Weights& w = lv.l1w[i];
+      fill(w.W, *W);
+      fill(w.KA, *KA);
+      fill(w.KS, *KS);
+      const std::vector<float>* ws = nsteps > 0 ? find(7, i + 1) : KS;
+      if (!ws) return fail(MCMG_E_WEIGHTS, "missing smoother tensor");
+      fill(w.Wsm, *ws);
+    }
+    lv.e_alt = (float*)alloc((size_t)lv.dims.total * 2 * sizeof(float));
+    if (!lv.e_alt) return fail(MCMG_E_OOM, "level allocation failed");
+  }
+  return MCMG_OK;
 }
 
 // Alg. 1: a_1 = f_lift(m), s_l = f_s(a_l), a_{l+1} = f_a(a_l).
@@ -279,6 +362,17 @@ hipError_t Ctx::run_setup() {
     }
   }
   return hipSuccess;
+}
+
+hipError_t Ctx::helm_timed(int tin, const void* u, const double* f, double* out, double* partial) {
+  const HelmOp op = helm();
+  const double N = (double)ext.total;
+  // algorithmic traffic: u, k^2 and the output (+ f in residual form)
+  const double bytes = N * ((tin == T_F64 ? 16.0 : 8.0) + 8.0 + 16.0 + (f ? 16.0 : 0.0));
+  const double flops = N * (dim == 2 ? 38.0 : 54.0);
+  const char* name = intern_name(std::string("helm_kernel<") + std::to_string(dim) + "," +
+                                 (tin == T_F64 ? "double" : "float") + ">");
+  return timed(name, flops, bytes, [&] { return launch_helm(op, tin, u, f, out, partial, stream); });
 }
 
 HelmOp Ctx::helm() const {
@@ -340,8 +434,6 @@ mcmg_status do_setup(const double* c, mcmg_grid grid, double omega, double h, mc
   }
   mcmg_status st = ctx->parse_weights(w.blob, w.bytes);
   if (st != MCMG_OK) return st;
-  if (!ctx->bf16_supported() && ctx->precision == MCMG_BF16)
-    return fail(MCMG_E_ARG, "BF16 path not available for this configuration");
   // level geometry: ceil halving per axis
   int side[3] = {ctx->next[0], ctx->next[1], ctx->next[2]};
   for (int l = 0; l < ctx->L; ++l) {
@@ -383,6 +475,10 @@ mcmg_status do_setup(const double* c, mcmg_grid grid, double omega, double h, mc
   }
   e = ctx->run_setup();
   if (e != hipSuccess) return fail(MCMG_E_HIP, "setup convolutions: %s", hipGetErrorString(e));
+  st = ctx->plan_mfma();
+  if (st != MCMG_OK) return st;
+  st = ctx->plan_level1();
+  if (st != MCMG_OK) return st;
   st = ctx->alloc_krylov();
   if (st != MCMG_OK) return st;
   e = hipStreamSynchronize(s);
@@ -423,7 +519,6 @@ mcmg_status Ctx::alloc_krylov() {
   return MCMG_OK;
 }
 
-bool Ctx::bf16_supported() const { return true; }
 
 }  // namespace mcmg
 
@@ -477,8 +572,53 @@ mcmg_status mcmg_matvec(mcmg_handle h, const double* u, double* Au) {
   if (!h || !u || !Au) return fail(MCMG_E_ARG, "null argument");
   if ((const void*)u == (const void*)Au) return fail(MCMG_E_ARG, "u and Au may not alias");
   Ctx* c = (Ctx*)h;
-  hipError_t e = launch_helm(c->helm(), T_F64, u, nullptr, Au, nullptr, c->stream);
+  hipError_t e = c->helm_timed(T_F64, u, nullptr, Au, nullptr);
   if (e != hipSuccess) return fail(MCMG_E_HIP, "matvec: %s", hipGetErrorString(e));
+  return MCMG_OK;
+}
+
+mcmg_status mcmg_prof_enable(mcmg_handle h, int on) {
+  if (!h) return fail(MCMG_E_ARG, "null handle");
+  Ctx* c = (Ctx*)h;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(MCMG_E_HIP, "prof: %s", hipGetErrorString(e));
+  c->prof.on = on != 0;
+  c->prof.recs.clear();
+  c->prof.used = 0;
+  return MCMG_OK;
+}
+
+mcmg_status mcmg_prof_report(mcmg_handle h, char* buf, size_t cap) {
+  if (!h || !buf || cap == 0) return fail(MCMG_E_ARG, "null argument");
+  Ctx* c = (Ctx*)h;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(MCMG_E_HIP, "prof: %s", hipGetErrorString(e));
+  struct Agg { long long n = 0; double ms = 0, fl = 0, by = 0; };
+  std::map<std::string, Agg> agg;
+  for (const ProfRec& r : c->prof.recs) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess) return fail(MCMG_E_HIP, "prof: %s", hipGetErrorString(e));
+    Agg& a = agg[r.name];
+    a.n += 1; a.ms += ms; a.fl += r.flops; a.by += r.bytes;
+  }
+  std::string out = "[";
+  bool first = true;
+  for (auto& kv : agg) {
+    char line[512];
+    snprintf(line, sizeof(line),
+             "%s{\"name\":\"%s\",\"launches\":%lld,\"total_ms\":%.6f,\"avg_ms\":%.6f,"
+             "\"flops_per_launch\":%.6e,\"bytes_per_launch\":%.6e}",
+             first ? "" : ",", kv.first.c_str(), kv.second.n, kv.second.ms,
+             kv.second.ms / kv.second.n, kv.second.fl / kv.second.n, kv.second.by / kv.second.n);
+    out += line;
+    first = false;
+  }
+  out += "]";
+  if (out.size() + 1 > cap) return fail(MCMG_E_ARG, "report buffer too small (%zu bytes needed)", out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
+  c->prof.recs.clear();
+  c->prof.used = 0;
   return MCMG_OK;
 }
 

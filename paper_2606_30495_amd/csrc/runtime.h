@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "internal.h"
@@ -11,6 +12,14 @@
 namespace mcmg {
 
 mcmg_status fail(mcmg_status s, const char* fmt, ...);
+
+// One matrix-core convolution instance: shapes, packing and tile choice.
+struct MOp {
+  bool on = false;
+  int mode = 0, epi = 0, cin = 0, cout = 0, cinp = 0, ncols = 0, npairs = 0, nsteps = 0;
+  int mt = 2, ntw = 1;
+  Dims in{}, out{};
+};
 
 struct Level {
   int n[3] = {1, 1, 1};
@@ -22,6 +31,41 @@ struct Level {
   float *w_fs = nullptr, *w_W = nullptr, *w_KA = nullptr, *w_KS = nullptr;
   std::vector<float*> w_sm;
   float *w_fa = nullptr, *w_R = nullptr, *w_P = nullptr;
+  // matrix-core plans and packed weights (op.on == false: VALU path)
+  MOp op_resid, op_mul, op_set, op_add;   // stride-1 solve convolutions
+  MOp op_R;                                // restriction this level -> next
+  MOp op_P;                                // prolongation next level -> this
+  void *m_W = nullptr, *m_KA = nullptr, *m_KS = nullptr, *m_R = nullptr, *m_P = nullptr;
+  std::vector<void*> m_sm;
+  // fused C = 2 sweep: per smoothing step weights; e ping-pongs with e_alt
+  std::vector<L1Weights> l1w;
+  float* e_alt = nullptr;
+};
+
+// Optional per-launch timing with HIP events on the handle's stream, with
+// the algorithmic work of every launch (flops, bytes) from its shapes.
+struct ProfRec {
+  const char* name;
+  double flops, bytes;
+  hipEvent_t a, b;
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  ~Prof() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 struct HostTensor {
@@ -59,23 +103,47 @@ struct Ctx {
 
   std::vector<void*> allocs;
   size_t device_bytes = 0;
+  Prof prof;
+
+  template <class F>
+  hipError_t timed(const char* name, double flops, double bytes, F&& launch) {
+    if (!prof.on) return launch();
+    hipEvent_t a = prof.get(), b = prof.get();
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, stream);
+    prof.recs.push_back({name, flops, bytes, a, b});
+    return e;
+  }
 
   ~Ctx();
   void* alloc(size_t bytes);
   mcmg_status parse_weights(const void* blob, size_t bytes);
   mcmg_status upload_weight(const float* src, int d0, int d1, bool transposed, float** dst);
   mcmg_status alloc_krylov();
-  bool bf16_supported() const;
   hipError_t on_features_changed() { return hipSuccess; }
 
   hipError_t conv(int mode, int epi, int tin, const void* x, const Dims& in, int cin,
                   const float* w, const float* w2, int tout, void* y, const Dims& out, int cout,
                   const float* r, const float* feat);
+  // stride-1 solve convolution on level lv: matrix cores when packed, else VALU
+  hipError_t conv_level(Level& lv, int epi, const float* x, const float* w, const void* wm,
+                        const float* w2, const void* wm2, float* y, const float* r,
+                        const float* feat);
+  mcmg_status plan_mfma();                 // pack weights, choose tiles (autotune)
+  hipError_t run_mop(const MOp& op, const float* x, const void* wA, const void* wB, float* y,
+                     const float* r, const float* feat);
   hipError_t dispatch_conv(const ConvLaunch& a);
   hipError_t vcycle(const void* rin, int tin, void* zout, int tout);
   hipError_t smooth_step(Level& lv, int i, bool first);
+  hipError_t level1(Level& lv, int var, int step);   // fused C = 2 sweep
+  mcmg_status plan_level1();
   hipError_t run_setup();
   HelmOp helm() const;
+  hipError_t helm_timed(int tin, const void* u, const double* f, double* out, double* partial);
 };
 
 }  // namespace mcmg

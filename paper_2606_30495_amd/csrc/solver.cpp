@@ -60,7 +60,7 @@ hipError_t norm_sq(Ctx* c, const double* x, double* out) {
 // r = f - A u and |r| -> scal[3]
 hipError_t true_residual(Ctx* c, const double* f, const double* u) {
   HelmOp op = c->helm();
-  hipError_t e = launch_helm(op, T_F64, u, f, c->rv, c->partial, c->stream);
+  hipError_t e = c->helm_timed(T_F64, u, f, c->rv, c->partial);
   if (e != hipSuccess) return e;
   return launch_reduce_sum(c->partial, helm_blocks(op), c->scal + 2, c->stream);
 }
@@ -114,20 +114,25 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       double* Vj = c->V + 2LL * j * N;
       float* Zj = c->Z + 2LL * j * N;
       HCK(c->vcycle(Vj, T_F64, Zj, T_F32));
-      HCK(launch_helm(op, T_F32, Zj, nullptr, c->wv, nullptr, s));
+      HCK(c->helm_timed(T_F32, Zj, nullptr, c->wv, nullptr));
       ++its;
       double* Hcol = c->H + 2LL * j * ldh;
       const int nv = j + 1;
       const int nb = c->nb_red;
       // pass 0 (always) and pass 1 (device-gated re-orthogonalisation)
-      HCK(launch_multidot(c->V, N, nv, c->wv, N, c->partial, nullptr, s));
+      const double vb = 16.0 * (double)N;
+      HCK(c->timed("multidot_kernel", 8.0 * N * (nv + 1), vb * (nv + 1),
+                   [&] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, nullptr, s); }));
       HCK(launch_reduce_dots(c->partial, nb, nv, c->coef, Hcol, c->scal + 8, nullptr, s));
-      HCK(launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, nullptr, s));
+      HCK(c->timed("update_kernel", 8.0 * N * (nv + 1), vb * (nv + 2),
+                   [&] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, nullptr, s); }));
       HCK(launch_reduce_norm(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, 0,
                              c->ortho == 1, s));
-      HCK(launch_multidot(c->V, N, nv, c->wv, N, c->partial, c->skip, s));
+      HCK(c->timed("multidot_kernel(reorth)", 8.0 * N * (nv + 1), vb * (nv + 1),
+                   [&] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, c->skip, s); }));
       HCK(launch_reduce_dots(c->partial, nb, nv, c->coef, Hcol, c->scal + 10, c->skip, s));
-      HCK(launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, c->skip, s));
+      HCK(c->timed("update_kernel(reorth)", 8.0 * N * (nv + 1), vb * (nv + 2),
+                   [&] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, c->skip, s); }));
       HCK(launch_reduce_norm(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, 1, 0, s));
       HCK(launch_givens(c->H, ldh, j, c->scal + 9, c->cs, c->sn, c->g, c->scal + 16, s));
       if (j + 1 < m) HCK(launch_scale(c->wv, c->scal + 9, c->V + 2LL * (j + 1) * N, N, s));
@@ -141,7 +146,8 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       if (rho <= target || hn <= 1e-14 * cn || its >= maxit) break;
     }
     HCK(launch_backsolve(c->H, ldh, k, c->g, c->y, s));
-    HCK(launch_zupdate(c->Z, N, k, c->y, u, N, s));
+    HCK(c->timed("zupdate_kernel", 8.0 * N * k, (8.0 * k + 32.0) * N,
+                 [&] { return launch_zupdate(c->Z, N, k, c->y, u, N, s); }));
     HCK(true_residual(c, f, u));
     HCK(read_scal(c, 3, 1));
     beta = c->host_scal[0];

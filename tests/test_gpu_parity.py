@@ -97,6 +97,24 @@ def test_apply_matches_oracle(name):
     assert err <= 1e-5, err
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_bf16_within_budget(name):
+    """bf16 matrix-core operands with float32 accumulation and float32 state:
+    per-application error against the FP64 oracle within 2e-2."""
+    dim, n, npml, ch = CASES[name]
+    say(f"[apply-bf16] {name}")
+    p = problem(dim, n, npml, ch)
+    op, W, M = oracle_parts(p)
+    H = handle(p, precision="bf16")
+    r = synth.random_rhs(H.ext_shape, 3)
+    z = to_dev(np.zeros_like(r))
+    H.apply(to_dev(r), z)
+    err = rel_l2(to_host(z), M(r))
+    say(f"  relL2 = {err:.3e}")
+    assert err <= 2e-2, err
+    assert err > 1e-6      # the bf16 path really rounds
+
+
 def test_apply_linear_and_deterministic():
     """Linearity in r over the reals (Sec. 3.2) survives FP32 to rounding
     level; two runs give bitwise identical output."""
