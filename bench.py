@@ -32,7 +32,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="grf1024")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--single", action="store_true", help="skip the other-precision leg")
+    ap.add_argument("--solves", type=int, default=50,
+                    help="right-hand sides of the solve-to-tolerance leg (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     return ap.parse_args()
@@ -44,7 +47,7 @@ def roofline_for(rec, precision):
     under (ridge = peak flops / peak bytes)."""
     fl, by, ms = rec["flops_per_launch"], rec["bytes_per_launch"], rec["avg_ms"]
     name = rec["name"]
-    if name.startswith("mconv_kernel") and "bf16" in name:
+    if name.startswith("mconv_kernel<") and ", true," in name:
         peak_fl, unit_bound = PEAK_BF16_TFLOPS, "mfma"
     elif name.startswith("mconv_kernel"):
         peak_fl, unit_bound = PEAK_FP32_TFLOPS, "mfma"
@@ -61,6 +64,115 @@ def roofline_for(rec, precision):
     ach = fl / (ms * 1e-3) / 1e12
     return {"bound": unit_bound, "achieved": round(ach, 3), "peak": peak_fl, "unit": "TFLOP/s",
             "frac": round(ach / peak_fl, 4), "traffic": None}
+
+
+def run_leg(cfg, c, omega, h, f, blob, precision, steps, warmup):
+    """Setup, warm up, then time one solve of `steps` iterations from u = 0;
+    repeat it with per-launch HIP-event timing for the kernel breakdown."""
+    import torch
+    from paper_2606_30495_amd import Handle
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = Handle(c, omega, h, cfg.npml, blob, precision=precision, restart=cfg.restart)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    fd = torch.from_numpy(f).to("cuda")
+    ud = torch.zeros_like(fd)
+    if warmup > 0:
+        H.solve(fd, ud, tol=cfg.tol, maxit=warmup, hist_cap=0)
+    ud.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = H.solve(fd, ud, tol=cfg.tol, maxit=steps, hist_cap=0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    iters = info["iters"]
+    ud.zero_()
+    H.prof_enable(True)
+    H.solve(fd, ud, tol=cfg.tol, maxit=steps, hist_cap=0)
+    recs = H.prof_report()
+    recs.sort(key=lambda r: -r["total_ms"])
+    # live average duration of the dominant kernel: its recorded launches
+    # replayed back to back between one HIP event pair on the handle's stream
+    replay_ms, replay_n = H.prof_replay(recs[0]["name"], reps=3)
+    recs[0]["event_pair_avg_ms"] = recs[0]["avg_ms"]
+    recs[0]["avg_ms"] = replay_ms
+    recs[0]["replayed_launches"] = replay_n
+    H.prof_enable(False)
+    H.close()
+    return {"value": iters / el, "ms_per_step": el / max(iters, 1) * 1e3, "iters": iters,
+            "info": info, "recs": recs, "setup_ms": setup_ms}
+
+
+def solves_leg(precision, nrhs, seed=5):
+    """Solve-to-tolerance throughput on the small workload (64^2 interior,
+    8-cell PML, Gaussian bump, 3 levels 2/8/16): random-init weights never
+    reach 1e-6, so this leg runs the same V-cycle with hand-set classical
+    coefficients (shifted-Laplacian multigrid in McMg's tensor structure,
+    synth.classical).  nrhs point sources at seeded random interior nodes,
+    each solved from u = 0 to true relative residual 1e-6, one after another;
+    latency = call to return."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_30495_amd import Handle
+    cfg = synth.CONFIGS["bump64"]
+    c, omega, h, _ = synth.make_problem(cfg)
+    tens, feats = synth.shifted_laplacian(c, omega, h, cfg.npml, cfg.channels, cfg.nu1, cfg.nu2)
+    blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
+    H = Handle(c, omega, h, cfg.npml, blob, precision=precision, restart=cfg.restart)
+    for l, (a, s) in enumerate(feats, start=1):
+        H.set_features(l, torch.from_numpy(a).cuda(), torch.from_numpy(s).cuda())
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fs = [torch.from_numpy(synth.point_source(cfg.n, cfg.npml, tuple(rng.uniform(0.1, 0.9, 2)), 2)).cuda()
+          for _ in range(nrhs)]
+    u = torch.zeros_like(fs[0])
+    H.solve(fs[0], u, tol=cfg.tol, maxit=cfg.maxit, hist_cap=0)   # warm-up
+    lat, its, ok, worst = [], [], 0, 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in fs:
+        u.zero_()
+        t1 = time.perf_counter()
+        info = H.solve(f, u, tol=cfg.tol, maxit=cfg.maxit, hist_cap=0)
+        lat.append(time.perf_counter() - t1)
+        its.append(info["iters"])
+        ok += int(info["converged"])
+        worst = max(worst, info["relres_true"])
+    el = time.perf_counter() - t0
+    H.close()
+    lat = np.array(lat) * 1e3
+    return {"workload": "bump64 (64^2 + 8-cell PML, 3 levels 2/8/16), classical coefficients",
+            "precision": precision, "nrhs": nrhs, "solves_per_s": round(ok / el, 3),
+            "iters_per_s": round(sum(its) / el, 2), "mean_iters": round(float(np.mean(its)), 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "converged": ok, "max_relres_true": worst}
+
+
+def traffic_for(kernel):
+    """Counter-measured HBM bytes per launch of `kernel` from the committed
+    rocprofv3 summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration); None when absent or when the kernel source changed since."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+    if not m:
+        return None
+    try:
+        table = json.loads(m.group(1))
+    except ValueError:
+        return None
+    ent = table.get("kernels", {}).get(kernel)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != ent["sha256"]:
+        return None
+    return ent["bytes_per_launch"]
 
 
 def cpu_baseline(cfg, c, omega, h, f, tens, iters):
@@ -97,51 +209,28 @@ def main():
               "(independent solves shard across GPUs without communication; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     import synth
-    from paper_2606_30495_amd import Handle
 
     cfg = synth.CONFIGS[a.config]
     c, omega, h, f = synth.make_problem(cfg)
     tens = synth.make_weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, cfg.weight_seed)
     blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
 
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    H = Handle(c, omega, h, cfg.npml, blob, precision=a.precision, restart=cfg.restart)
-    torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-
-    fd = torch.from_numpy(f).to("cuda")
-    ud = torch.zeros_like(fd)
-    if a.warmup > 0:
-        H.solve(fd, ud, tol=cfg.tol, maxit=a.warmup, hist_cap=0)
-    # timed region: one solve of K iterations from u = 0
-    ud.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = H.solve(fd, ud, tol=cfg.tol, maxit=a.steps, hist_cap=0)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    iters = info["iters"]
-    value = iters / el
-    # same solve again with per-launch HIP-event timing for the kernel breakdown
-    ud.zero_()
-    H.prof_enable(True)
-    H.solve(fd, ud, tol=cfg.tol, maxit=a.steps, hist_cap=0)
-    recs = H.prof_report()
-    H.prof_enable(False)
-    recs.sort(key=lambda r: -r["total_ms"])
+    head = run_leg(cfg, c, omega, h, f, blob, a.precision, a.steps, a.warmup)
+    other = "fp32" if a.precision == "bf16" else "bf16"
+    cmp_leg = None if a.single else run_leg(cfg, c, omega, h, f, blob, other, a.steps, a.warmup)
+    recs = head["recs"]
     dom = recs[0]
     roof = roofline_for(dom, a.precision)
+    roof["traffic"] = traffic_for(dom["name"])
     roof["kernel"] = dom["name"]
-    roof["launches_per_step"] = round(dom["launches"] / max(iters, 1), 2)
+    roof["launches_per_step"] = round(dom["launches"] / max(head["iters"], 1), 2)
     roof["avg_launch_us"] = round(dom["avg_ms"] * 1e3, 3)
     line = {
         "metric": "FGMRES+V-cycle iters/s (solves/s to rel-res 1e-6; p50/p99 solve latency)",
-        "value": round(value, 3), "unit": "iters/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": round(el / max(iters, 1) * 1e3, 4),
+        "value": round(head["value"], 3), "unit": "iters/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(head["ms_per_step"], 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if a.precision == "fp32" else "bf16",
         "data": "synthetic (seeded medium, random-init weights N(0,1/fan_in) seed 0)",
@@ -149,12 +238,21 @@ def main():
                    "n_ext": cfg.n_ext, "levels": cfg.levels, "channels": list(cfg.channels),
                    "nu": [cfg.nu1[0], cfg.nu2[0]], "restart": cfg.restart,
                    "precision": a.precision, "outer": "f64"},
-        "solve": {"iters": iters, "relres_true": info["relres_true"],
-                  "converged": info["converged"], "setup_ms": round(setup_ms, 2)},
+        "solve": {"iters": head["iters"], "relres_true": head["info"]["relres_true"],
+                  "converged": head["info"]["converged"], "setup_ms": round(head["setup_ms"], 2)},
         "roofline": roof,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                     for r in recs[:16]],
     }
+    if a.solves > 0:
+        line["solves"] = [solves_leg(a.precision, a.solves)]
+        if not a.single:
+            line["solves"].append(solves_leg(other, a.solves))
+    if cmp_leg is not None:
+        line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
+                           "ms_per_step": round(cmp_leg["ms_per_step"], 4),
+                           "relres_true": cmp_leg["info"]["relres_true"],
+                           "dominant_kernel": cmp_leg["recs"][0]["name"]}
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(cfg, c, omega, h, f, tens, a.cpu_iters)
     else:

@@ -144,9 +144,17 @@ const char* mcmg_last_error(void);
  * shapes, not counters); mcmg_prof_report() synchronises, aggregates the
  * records per kernel symbol into a JSON array of {name, launches, total_ms,
  * avg_ms, flops_per_launch, bytes_per_launch} written to buf (host, cap
- * bytes), and clears them.  E_ARG if buf is too small. */
+ * bytes).  E_ARG if buf is too small.  mcmg_prof_enable() (on or off)
+ * clears the records.  mcmg_prof_replay() re-issues the recorded launches of
+ * the kernel `name`, reps times, back to back between ONE event pair on the
+ * handle's stream and returns the average duration per launch (without the
+ * per-launch event overhead of the records); the replayed launches write the
+ * handle's work buffers and the caller's buffers they name, so call it
+ * between solves. */
 mcmg_status mcmg_prof_enable(mcmg_handle h, int on);
 mcmg_status mcmg_prof_report(mcmg_handle h, char* buf, size_t cap);
+mcmg_status mcmg_prof_replay(mcmg_handle h, const char* name, int reps, double* avg_ms,
+                             int* launches);
 
 /* Test hooks: replace / read level l's (1-based) cached features a_l, s_l
  * (device float32 [nodes][C_l], row-major nodes, channel fastest).  Used to

@@ -73,6 +73,9 @@ EXPORTS = {
     "mcmg_last_error": (ctypes.c_char_p, []),
     "mcmg_prof_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "mcmg_prof_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_size_t]),
+    "mcmg_prof_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int)]),
     "mcmg_debug_set_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                                ctypes.c_void_p]),
     "mcmg_debug_get_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -196,6 +199,13 @@ class Handle:
         buf = ctypes.create_string_buffer(1 << 20)
         _check(lib().mcmg_prof_report(self.ptr, buf, len(buf)))
         return json.loads(buf.value.decode())
+
+    def prof_replay(self, name, reps=1):
+        avg = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(lib().mcmg_prof_replay(self.ptr, name.encode(), int(reps), ctypes.byref(avg),
+                                      ctypes.byref(n)))
+        return avg.value, n.value
 
     def level_shape(self, level):
         n = (ctypes.c_int * 3)()

@@ -66,17 +66,15 @@ struct Geo {
 };
 
 template <bool BF> constexpr int KVOF() { return BF ? 8 : 1; }
-template <bool BF> constexpr int KSOF() { return BF ? 6 : 24; }   // K-steps per weight chunk
 
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
 __global__ __launch_bounds__(256) void mconv_kernel(
     const float* __restrict__ x, const void* __restrict__ wA, const void* __restrict__ wB,
     float* __restrict__ y, const float* __restrict__ r, const float* __restrict__ feat, int cin,
     int cinp, int cout, int ncols, int nsteps, int npairs, Dims in, Dims out, int tiles_x,
-    int tiles_y, int tiles_z) {
+    int tiles_y, int tiles_z, int kchunk) {
   using G = Geo<D, MODE, MT>;
   constexpr int KV = KVOF<BF>();
-  constexpr int KS = KSOF<BF>();
   constexpr int NACC = (EPI == EPI_RESID) ? 2 : 1;
   constexpr int ES = BF ? 2 : 4;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -103,36 +101,47 @@ __global__ __launch_bounds__(256) void mconv_kernel(
   else { sx = x0; sy = y0; sz = z0; }
   if (D == 2) sz = 0;
 
-  // ---- stage the input tile
+  // ---- stage the input tile: loads are issued in batches of SB per thread
+  // before any LDS store, so a block waits for one memory latency per batch
   {
+    constexpr int SB = 8;
     const bool vec4 = (cin % 4) == 0;
     const int ng = cinp / 4;
-    for (int idx = threadIdx.x; idx < G::NODES * ng; idx += 256) {
-      const int node = idx / ng, c = (idx % ng) * 4;
-      const int hx = node % G::HX, hy = (node / G::HX) % G::HY, hz = node / (G::HX * G::HY);
-      const int gx = sx + hx, gy = sy + hy, gz = sz + hz;
-      float v[4] = {0.f, 0.f, 0.f, 0.f};
-      if (gx >= 0 && gx < IX && gy >= 0 && gy < IY && gz >= 0 && gz < IZ) {
-        const long long g = (((long long)gz * IY + gy) * IX + gx) * cin;
-        if (vec4) {
-          if (c < cin) {
-            const float4 t = *reinterpret_cast<const float4*>(x + g + c);
-            v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-          }
-        } else {
+    const int total = G::NODES * ng;
+    for (int base = threadIdx.x; base < total; base += 256 * SB) {
+      float4 v[SB];
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
-            if (c + k < cin) v[k] = x[g + c + k];
+      for (int k = 0; k < SB; ++k) {
+        v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        const int hx = node % G::HX, hy = (node / G::HX) % G::HY, hz = node / (G::HX * G::HY);
+        const int gx = sx + hx, gy = sy + hy, gz = sz + hz;
+        if (gx >= 0 && gx < IX && gy >= 0 && gy < IY && gz >= 0 && gz < IZ && c < cin) {
+          const long long g = (((long long)gz * IY + gy) * IX + gx) * cin;
+          if (vec4) {
+            v[k] = *reinterpret_cast<const float4*>(x + g + c);
+          } else {
+            v[k].x = x[g + c];
+            if (c + 1 < cin) v[k].y = x[g + c + 1];
+            if (c + 2 < cin) v[k].z = x[g + c + 2];
+            if (c + 3 < cin) v[k].w = x[g + c + 3];
+          }
         }
       }
-      if constexpr (BF) {
-        u16* s = reinterpret_cast<u16*>(smem) + (size_t)node * stride + c;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] = f2bf(v[k]);
-      } else {
-        float* s = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) s[k] = v[k];
+      for (int k = 0; k < SB; ++k) {
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        if constexpr (BF) {
+          u16* s = reinterpret_cast<u16*>(smem) + (size_t)node * stride + c;
+          s[0] = f2bf(v[k].x); s[1] = f2bf(v[k].y); s[2] = f2bf(v[k].z); s[3] = f2bf(v[k].w);
+        } else {
+          float* s = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
+          s[0] = v[k].x; s[1] = v[k].y; s[2] = v[k].z; s[3] = v[k].w;
+        }
       }
     }
   }
@@ -151,21 +160,36 @@ __global__ __launch_bounds__(256) void mconv_kernel(
       for (int t = 0; t < NTW; ++t) acc[a][m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   const int cpv = cinp / KV;
+  const int KS = kchunk;
   for (int s0 = 0; s0 < nsteps; s0 += KS) {
     const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
     __syncthreads();   // previous chunk consumed (and input tile staged)
     {
       // weight chunk rows q in [4 s0, 4 (s0 + ks)), columns [col0, col0 + 16 NTW)
+      constexpr int SB = 8;
       const int nrow = 4 * ks;
       constexpr int V16 = BROW * ES / 16;    // 16-byte vectors per row
-      for (int idx = threadIdx.x; idx < NACC * nrow * V16; idx += 256) {
-        const int a = idx / (nrow * V16);
-        const int rem = idx % (nrow * V16);
-        const int row = rem / V16, v = rem % V16;
-        const unsigned char* src = reinterpret_cast<const unsigned char*>(a ? wB : wA) +
-                                   (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)v * 16;
-        unsigned char* dst = bsm + (((size_t)a * 4 * KS + row) * BROW) * ES + (size_t)v * 16;
-        *reinterpret_cast<uint4*>(dst) = *reinterpret_cast<const uint4*>(src);
+      const int total = NACC * nrow * V16;
+      for (int base = threadIdx.x; base < total; base += 256 * SB) {
+        uint4 v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          if (idx >= total) continue;
+          const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
+          const int row = rem / V16, vv = rem % V16;
+          v[k] = *reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(a ? wB : wA) +
+                                                 (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES +
+                                                 (size_t)vv * 16);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          if (idx >= total) continue;
+          const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
+          const int row = rem / V16, vv = rem % V16;
+          *reinterpret_cast<uint4*>(bsm + (((size_t)a * 4 * KS + row) * BROW) * ES + (size_t)vv * 16) = v[k];
+        }
       }
     }
     __syncthreads();
@@ -259,9 +283,9 @@ hipError_t run(const MfmaConv& a, hipStream_t s) {
   const int nblk = ((ntiles + 7) / 8) * 8;
   const int nslices = a.ncols / (16 * NTW);
   hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW>), dim3(nblk, nslices), dim3(256),
-                     mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi), s, a.x, a.wA,
+                     mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi, a.kchunk), s, a.x, a.wA,
                      a.wB, a.y, a.r, a.feat, a.cin, a.cinp, a.cout, a.ncols, a.nsteps, a.npairs, a.in,
-                     a.out, tx, ty, tz);
+                     a.out, tx, ty, tz, a.kchunk);
   return hipGetLastError();
 }
 
@@ -304,11 +328,11 @@ hipError_t by_mode(const MfmaConv& a, hipStream_t s) {
 
 }  // namespace
 
-size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi) {
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi, int kchunk) {
   const int TX = 16 * mt, TY = dim == 2 ? 4 : 2, TZ = dim == 2 ? 1 : 2;
   auto ext = [&](int t) { return mode == CONV_S1 ? t + 2 : (mode == CONV_S2 ? 2 * t + 1 : t + 1); };
   const size_t nodes = (size_t)ext(TX) * ext(TY) * (dim == 2 ? 1 : ext(TZ));
-  const int es = bf16 ? 2 : 4, kv = bf16 ? 8 : 1, ks = bf16 ? 6 : 24;
+  const int es = bf16 ? 2 : 4, kv = bf16 ? 8 : 1, ks = kchunk;
   const size_t stride = cinp + (bf16 ? 8 : 1);
   const size_t a = ((nodes * stride * es + 15) / 16) * 16;
   const size_t b = (size_t)(epi == EPI_RESID ? 2 : 1) * 4 * ks * ntw * 16 * kv * es;
@@ -335,11 +359,11 @@ hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s) {
 }
 
 const char* mfma_kernel_name(const MfmaConv& a) {
-  static const char* mode_s[3] = {"S1", "S2", "T2"};
-  static const char* epi_s[5] = {"SET", "ADD", "MUL", "GELU", "RESID"};
-  return intern_name(std::string("mconv_kernel<") + std::to_string(a.dim) + "," +
-                     (a.bf16 ? "bf16" : "f32") + "," + mode_s[a.mode] + "," + epi_s[a.epi] + "," +
-                     std::to_string(a.mt) + "," + std::to_string(a.ntw) + ">");
+  // the demangled template form profilers print
+  return intern_name(std::string("mconv_kernel<") + std::to_string(a.dim) + ", " +
+                     (a.bf16 ? "true" : "false") + ", " + std::to_string(a.mode) + ", " +
+                     std::to_string(a.epi) + ", " + std::to_string(a.mt) + ", " +
+                     std::to_string(a.ntw) + ">");
 }
 
 }  // namespace mcmg

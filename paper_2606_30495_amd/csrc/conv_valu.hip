@@ -182,13 +182,12 @@ hipError_t launch_zero_f64(double* p, long long n, hipStream_t s) {
 namespace mcmg {
 
 const char* conv_kernel_name(const ConvLaunch& a) {
-  static const char* mode_s[3] = {"S1", "S2", "T2"};
-  static const char* epi_s[5] = {"SET", "ADD", "MUL", "GELU", "RESID"};
-  static const char* ty_s[3] = {"f32", "f64", "bf16"};
+  // the demangled template form profilers print
+  static const char* ty_s[3] = {"float", "double", "bf16"};
   const int ct = conv_chunk(a.cout);
-  return intern_name(std::string("conv_direct<") + std::to_string(a.dim) + "," +
-                     std::to_string(ct) + "," + mode_s[a.mode] + "," + epi_s[a.epi] + "," +
-                     ty_s[a.tin] + "," + ty_s[a.tout] + ">");
+  return intern_name(std::string("conv_direct<") + std::to_string(a.dim) + ", " +
+                     std::to_string(ct) + ", " + std::to_string(a.mode) + ", " +
+                     std::to_string(a.epi) + ", " + ty_s[a.tin] + ", " + ty_s[a.tout] + ">");
 }
 
 void conv_work(const ConvLaunch& a, double* flops, double* bytes) {

@@ -12,6 +12,11 @@
 // (8 bytes): 40 B/node, the HBM-bound sweep of the V-cycle.  e' goes to a
 // second buffer (neighbouring blocks still read e).
 //
+// Each phase runs tap-outermost: a thread owns a fixed set of points of the
+// phase's box and keeps their accumulators in registers, so only one tap's
+// 2 x 2 (x 2) weights are live at a time (wave-uniform scalars) and every
+// tap costs one LDS read plus the FMAs per point.
+//
 // Variants: FIRST (e = 0: u = s (.) (KS * r), e' = Wsm * u) and RESID
 // (t = r - A e only, the input of the restriction).
 #include "internal.h"
@@ -24,22 +29,28 @@ template <int D> struct G1;
 template <> struct G1<2> { static constexpr int TZ = 1, TY = 32, TX = 64; };
 template <> struct G1<3> { static constexpr int TZ = 2, TY = 4, TX = 32; };
 
+constexpr int NTH = 256;
+
 template <int D, int VAR>
-__global__ __launch_bounds__(256) void l1_kernel(const float2* __restrict__ e, float2* __restrict__ eo,
+__global__ __launch_bounds__(NTH) void l1_kernel(const float2* __restrict__ e, float2* __restrict__ eo,
                                                  const float2* __restrict__ r, const float2* __restrict__ a,
                                                  const float2* __restrict__ s, L1Weights w, Dims n,
                                                  int tiles_x, int tiles_y, int tiles_z) {
   using G = G1<D>;
   constexpr int T = (D == 2) ? 9 : 27;
   constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // halo of the staged e
-  // staged boxes: e (halo H), t (halo 2), u (halo 1); 2D uses no z halo
-  constexpr int HZ = (D == 2) ? 0 : 1;
+  constexpr int HZ = (D == 2) ? 0 : 1;                   // 2D has no z halo
+  // boxes: e (halo H), t (halo 2; RESID: the tile), u (halo 1), output tile
   constexpr int EZ = G::TZ + 2 * H * HZ, EY = G::TY + 2 * H, EX = G::TX + 2 * H;
-  constexpr int TZt = G::TZ + 4 * HZ, TYt = G::TY + 4, TXt = G::TX + 4;
+  constexpr int TG = (VAR == L1_RESID) ? 0 : 2;
+  constexpr int TZt = G::TZ + 2 * TG * HZ, TYt = G::TY + 2 * TG, TXt = G::TX + 2 * TG;
   constexpr int UZ = G::TZ + 2 * HZ, UY = G::TY + 2, UX = G::TX + 2;
-  __shared__ float2 se[(VAR == L1_FIRST) ? 1 : EZ * EY * EX];
-  __shared__ float2 st[(VAR == L1_RESID) ? 1 : TZt * TYt * TXt];
-  __shared__ float2 su[(VAR == L1_RESID) ? 1 : UZ * UY * UX];
+  constexpr int NE = EZ * EY * EX, NTB = TZt * TYt * TXt, NU = UZ * UY * UX;
+  constexpr int NO = G::TZ * G::TY * G::TX;
+  constexpr int PT = (NTB + NTH - 1) / NTH, PU = (NU + NTH - 1) / NTH, PO = (NO + NTH - 1) / NTH;
+  __shared__ float2 se[(VAR == L1_FIRST) ? 1 : NE];
+  __shared__ float2 st[(VAR == L1_RESID) ? 1 : NTB];
+  __shared__ float2 su[(VAR == L1_RESID) ? 1 : NU];
 
   const int NX = (D == 2) ? n.n[1] : n.n[2], NY = (D == 2) ? n.n[0] : n.n[1];
   const int NZ = (D == 2) ? 1 : n.n[0];
@@ -53,120 +64,160 @@ __global__ __launch_bounds__(256) void l1_kernel(const float2* __restrict__ e, f
     return x >= 0 && x < NX && y >= 0 && y < NY && z >= 0 && z < NZ;
   };
   auto gidx = [&](int z, int y, int x) { return ((long long)z * NY + y) * NX + x; };
-  auto off = [&](int t, int& dz, int& dy, int& dx) {
-    if (D == 2) { dz = 0; dy = t / 3 - 1; dx = t % 3 - 1; }
-    else { dz = t / 9 - 1; dy = (t / 3) % 3 - 1; dx = t % 3 - 1; }
-  };
+  const float2 zero = make_float2(0.f, 0.f);
 
-  // ---- stage e with halo H
+  // ---- stage e with halo H (all loads of a thread issued before the stores)
   if (VAR != L1_FIRST) {
+    constexpr int PE = (NE + NTH - 1) / NTH;
     const int oz = z0 - H * HZ, oy = y0 - H, ox = x0 - H;
-    for (int i = threadIdx.x; i < EZ * EY * EX; i += 256) {
+    float2 v[PE];
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int i = threadIdx.x + k * NTH;
       const int x = i % EX, y = (i / EX) % EY, z = i / (EX * EY);
-      const int gz = oz + z, gy = oy + y, gx = ox + x;
-      se[i] = inside(gz, gy, gx) ? e[gidx(gz, gy, gx)] : make_float2(0.f, 0.f);
+      v[k] = (i < NE && inside(oz + z, oy + y, ox + x)) ? e[gidx(oz + z, oy + y, ox + x)] : zero;
+    }
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NE) se[i] = v[k];
     }
     __syncthreads();
   }
 
-  // ---- t = r - W*e - a (.) (KA*e) on the tile grown by 2 (RESID: the tile)
-  if (VAR == L1_RESID) {
-    for (int i = threadIdx.x; i < G::TZ * G::TY * G::TX; i += 256) {
-      const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
-      const int gz = z0 + z, gy = y0 + y, gx = x0 + x;
-      if (!inside(gz, gy, gx)) continue;
-      float w0 = 0.f, w1 = 0.f, k0 = 0.f, k1 = 0.f;
+  // ---- t box: t = r - W*e - a (.) (KA*e)   (FIRST: t = r)
+  {
+    const int oz = z0 - TG * HZ, oy = y0 - TG, ox = x0 - TG;
+    float2 rv[PT], av[PT];
+    int eb[PT];                 // e-box index of the point (tap offset 0)
+    bool ok[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int x = i % TXt, y = (i / TXt) % TYt, z = i / (TXt * TYt);
+      ok[k] = i < NTB && inside(oz + z, oy + y, ox + x);
+      const long long g = gidx(oz + z, oy + y, ox + x);
+      rv[k] = ok[k] ? r[g] : zero;
+      av[k] = (ok[k] && VAR != L1_FIRST) ? a[g] : zero;
+      // t-box point (z, y, x) sits at e-box (z + (H-TG) HZ, y + H - TG, x + H - TG)
+      eb[k] = (i < NTB) ? ((z + (H - TG) * HZ) * EY + (y + H - TG)) * EX + (x + H - TG) : (HZ * EY + 1) * EX + 1;
+    }
+    float w0[PT], w1[PT], k0[PT], k1[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
+    if (VAR != L1_FIRST) {
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        int dz, dy, dx;
-        off(t, dz, dy, dx);
-        const float2 v = se[((z + 1 * HZ + dz) * EY + (y + 1 + dy)) * EX + (x + 1 + dx)];
-        w0 += w.W[0][0][t] * v.x + w.W[0][1][t] * v.y;
-        w1 += w.W[1][0][t] * v.x + w.W[1][1][t] * v.y;
-        k0 += w.KA[0][0][t] * v.x + w.KA[0][1][t] * v.y;
-        k1 += w.KA[1][0][t] * v.x + w.KA[1][1][t] * v.y;
-      }
-      const long long g = gidx(gz, gy, gx);
-      const float2 rv = r[g], av = a[g];
-      eo[g] = make_float2(rv.x - w0 - av.x * k0, rv.y - w1 - av.y * k1);
-    }
-    return;
-  }
-
-  {
-    const int oz = z0 - 2 * HZ, oy = y0 - 2, ox = x0 - 2;
-    for (int i = threadIdx.x; i < TZt * TYt * TXt; i += 256) {
-      const int x = i % TXt, y = (i / TXt) % TYt, z = i / (TXt * TYt);
-      const int gz = oz + z, gy = oy + y, gx = ox + x;
-      float2 tv = make_float2(0.f, 0.f);
-      if (inside(gz, gy, gx)) {
-        const long long g = gidx(gz, gy, gx);
-        const float2 rv = r[g];
-        if (VAR == L1_FIRST) {
-          tv = rv;
-        } else {
-          float w0 = 0.f, w1 = 0.f, k0 = 0.f, k1 = 0.f;
+        const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
+        const int dx = t % 3 - 1;
+        const int to = (dz * EY + dy) * EX + dx;
+        const float a00 = w.W[0][0][t], a01 = w.W[0][1][t], a10 = w.W[1][0][t], a11 = w.W[1][1][t];
+        const float b00 = w.KA[0][0][t], b01 = w.KA[0][1][t], b10 = w.KA[1][0][t], b11 = w.KA[1][1][t];
 #pragma unroll
-          for (int t = 0; t < T; ++t) {
-            int dz, dy, dx;
-            off(t, dz, dy, dx);
-            const float2 v = se[((z + HZ + dz) * EY + (y + 1 + dy)) * EX + (x + 1 + dx)];
-            w0 += w.W[0][0][t] * v.x + w.W[0][1][t] * v.y;
-            w1 += w.W[1][0][t] * v.x + w.W[1][1][t] * v.y;
-            k0 += w.KA[0][0][t] * v.x + w.KA[0][1][t] * v.y;
-            k1 += w.KA[1][0][t] * v.x + w.KA[1][1][t] * v.y;
-          }
-          const float2 av = a[g];
-          tv = make_float2(rv.x - w0 - av.x * k0, rv.y - w1 - av.y * k1);
+        for (int k = 0; k < PT; ++k) {
+          const float2 v = se[eb[k] + to];
+          w0[k] = fmaf(a00, v.x, fmaf(a01, v.y, w0[k]));
+          w1[k] = fmaf(a10, v.x, fmaf(a11, v.y, w1[k]));
+          k0[k] = fmaf(b00, v.x, fmaf(b01, v.y, k0[k]));
+          k1[k] = fmaf(b10, v.x, fmaf(b11, v.y, k1[k]));
         }
       }
-      st[i] = tv;
+    }
+    if (VAR == L1_RESID) {
+#pragma unroll
+      for (int k = 0; k < PT; ++k) {
+        const int i = threadIdx.x + k * NTH;
+        const int x = i % TXt, y = (i / TXt) % TYt, z = i / (TXt * TYt);
+        if (ok[k])
+          eo[gidx(oz + z, oy + y, ox + x)] = make_float2(rv[k].x - w0[k] - av[k].x * k0[k],
+                                                         rv[k].y - w1[k] - av[k].y * k1[k]);
+      }
+      return;
+    }
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NTB)
+        st[i] = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
+                      : zero;
     }
   }
   __syncthreads();
 
-  // ---- u = s (.) (KS * t) on the tile grown by 1
+  // ---- u box: u = s (.) (KS * t)
   {
     const int oz = z0 - HZ, oy = y0 - 1, ox = x0 - 1;
-    for (int i = threadIdx.x; i < UZ * UY * UX; i += 256) {
-      const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
-      const int gz = oz + z, gy = oy + y, gx = ox + x;
-      float2 uv = make_float2(0.f, 0.f);
-      if (inside(gz, gy, gx)) {
-        float c0 = 0.f, c1 = 0.f;
+    float2 sv[PU];
+    int tb[PU];
+    bool ok[PU];
 #pragma unroll
-        for (int t = 0; t < T; ++t) {
-          int dz, dy, dx;
-          off(t, dz, dy, dx);
-          const float2 v = st[((z + HZ + dz) * TYt + (y + 1 + dy)) * TXt + (x + 1 + dx)];
-          c0 += w.KS[0][0][t] * v.x + w.KS[0][1][t] * v.y;
-          c1 += w.KS[1][0][t] * v.x + w.KS[1][1][t] * v.y;
-        }
-        const float2 sv = s[gidx(gz, gy, gx)];
-        uv = make_float2(sv.x * c0, sv.y * c1);
+    for (int k = 0; k < PU; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
+      ok[k] = i < NU && inside(oz + z, oy + y, ox + x);
+      sv[k] = ok[k] ? s[gidx(oz + z, oy + y, ox + x)] : zero;
+      tb[k] = (i < NU) ? ((z + HZ) * TYt + (y + 1)) * TXt + (x + 1) : (HZ * TYt + 1) * TXt + 1;
+    }
+    float c0[PU], c1[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) c0[k] = c1[k] = 0.f;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
+      const int dx = t % 3 - 1;
+      const int to = (dz * TYt + dy) * TXt + dx;
+      const float a00 = w.KS[0][0][t], a01 = w.KS[0][1][t], a10 = w.KS[1][0][t], a11 = w.KS[1][1][t];
+#pragma unroll
+      for (int k = 0; k < PU; ++k) {
+        const float2 v = st[tb[k] + to];
+        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
+        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
       }
-      su[i] = uv;
+    }
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NU) su[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
     }
   }
   __syncthreads();
 
-  // ---- e' = e + Wsm * u on the tile
-  for (int i = threadIdx.x; i < G::TZ * G::TY * G::TX; i += 256) {
-    const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
-    const int gz = z0 + z, gy = y0 + y, gx = x0 + x;
-    if (!inside(gz, gy, gx)) continue;
-    float c0 = 0.f, c1 = 0.f;
+  // ---- output tile: e' = e + Wsm * u
+  {
+    int ub[PO];
+    bool ok[PO];
+#pragma unroll
+    for (int k = 0; k < PO; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
+      ok[k] = i < NO && inside(z0 + z, y0 + y, x0 + x);
+      ub[k] = (i < NO) ? ((z + HZ) * UY + (y + 1)) * UX + (x + 1) : (HZ * UY + 1) * UX + 1;
+    }
+    float c0[PO], c1[PO];
+#pragma unroll
+    for (int k = 0; k < PO; ++k) c0[k] = c1[k] = 0.f;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-      int dz, dy, dx;
-      off(t, dz, dy, dx);
-      const float2 v = su[((z + HZ + dz) * UY + (y + 1 + dy)) * UX + (x + 1 + dx)];
-      c0 += w.Wsm[0][0][t] * v.x + w.Wsm[0][1][t] * v.y;
-      c1 += w.Wsm[1][0][t] * v.x + w.Wsm[1][1][t] * v.y;
+      const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
+      const int dx = t % 3 - 1;
+      const int to = (dz * UY + dy) * UX + dx;
+      const float a00 = w.Wsm[0][0][t], a01 = w.Wsm[0][1][t], a10 = w.Wsm[1][0][t], a11 = w.Wsm[1][1][t];
+#pragma unroll
+      for (int k = 0; k < PO; ++k) {
+        const float2 v = su[ub[k] + to];
+        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
+        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+      }
     }
-    float2 ev = make_float2(0.f, 0.f);
-    if (VAR != L1_FIRST) ev = se[((z + H * HZ) * EY + (y + H)) * EX + (x + H)];
-    eo[gidx(gz, gy, gx)] = make_float2(ev.x + c0, ev.y + c1);
+#pragma unroll
+    for (int k = 0; k < PO; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (!ok[k]) continue;
+      const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
+      float2 ev = zero;
+      if (VAR != L1_FIRST) ev = se[((z + H * HZ) * EY + (y + H)) * EX + (x + H)];
+      eo[gidx(z0 + z, y0 + y, x0 + x)] = make_float2(ev.x + c0[k], ev.y + c1[k]);
+    }
   }
 }
 
@@ -177,7 +228,7 @@ hipError_t run(const L1Launch& l, hipStream_t s) {
   const int NZ = (D == 2) ? 1 : l.n.n[0];
   const int tx = (NX + G::TX - 1) / G::TX, ty = (NY + G::TY - 1) / G::TY, tz = (NZ + G::TZ - 1) / G::TZ;
   const int nt = tx * ty * tz;
-  hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(((nt + 7) / 8) * 8), dim3(256), 0, s,
+  hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(((nt + 7) / 8) * 8), dim3(NTH), 0, s,
                      (const float2*)l.e, (float2*)l.eo, (const float2*)l.r, (const float2*)l.a,
                      (const float2*)l.s, l.w, l.n, tx, ty, tz);
   return hipGetLastError();

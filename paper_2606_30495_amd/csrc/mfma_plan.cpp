@@ -8,8 +8,11 @@
 // handle's own buffers and timed with HIP events; the fastest is kept.
 // Choices are cached per process and, when MCMG_TUNE_CACHE names a file, in
 // that JSON file ({"key": [mt, ntw], ...}), keyed by
-// arch|dim|precision|mode|epi|cin|cout|grid.  MCMG_AUTOTUNE=0 skips timing
-// and takes the first fitting candidate.
+// arch|dim|precision|mode|epi|cin|cout|grid.  Without MCMG_TUNE_CACHE the
+// table tune_gfx950.json next to libmcmg.so (written by an earlier tuning
+// run) is read, so shapes it covers get the same tiles in every process.
+// MCMG_AUTOTUNE=0 skips timing and takes the first fitting candidate.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -39,12 +42,22 @@ const char* cache_path() {
   return (p && *p) ? p : nullptr;
 }
 
+// The tuning table shipped beside libmcmg.so (read only).
+std::string packaged_cache() {
+  Dl_info info;
+  if (!dladdr((void*)&packaged_cache, &info) || !info.dli_fname) return "";
+  std::string so = info.dli_fname;
+  const size_t slash = so.rfind('/');
+  return (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tune_gfx950.json";
+}
+
 void load_cache_locked() {
   if (g_tune_loaded) return;
   g_tune_loaded = true;
-  const char* p = cache_path();
-  if (!p) return;
-  std::ifstream f(p);
+  const char* env = cache_path();
+  const std::string path = env ? std::string(env) : packaged_cache();
+  if (path.empty()) return;
+  std::ifstream f(path);
   if (!f) return;
   std::stringstream ss;
   ss << f.rdbuf();
@@ -133,7 +146,7 @@ hipError_t Ctx::run_mop(const MOp& op, const float* x, const void* wA, const voi
   MfmaConv a;
   a.dim = dim;
   a.bf16 = precision == MCMG_BF16 ? 1 : 0;
-  a.mode = op.mode; a.epi = op.epi; a.mt = op.mt; a.ntw = op.ntw;
+  a.mode = op.mode; a.epi = op.epi; a.mt = op.mt; a.ntw = op.ntw; a.kchunk = op.kchunk;
   a.x = x; a.wA = wA; a.wB = wB; a.y = y; a.r = r; a.feat = feat;
   a.cin = op.cin; a.cinp = op.cinp; a.cout = op.cout; a.ncols = op.ncols;
   a.nsteps = op.nsteps; a.npairs = op.npairs;
@@ -151,7 +164,7 @@ hipError_t Ctx::run_mop(const MOp& op, const float* x, const void* wA, const voi
     const double extra = op.epi == EPI_RESID ? 2.0 : (op.epi == EPI_SET ? 0.0 : 1.0);
     by = 4.0 * ((double)op.in.total * op.cin + pout * (1.0 + extra));
   }
-  return timed(mfma_kernel_name(a), fl, by, [&] { return launch_conv_mfma(a, stream); });
+  return timed(mfma_kernel_name(a), fl, by, [=] { return launch_conv_mfma(a, stream); });
 }
 
 hipError_t Ctx::conv_level(Level& lv, int epi, const float* x, const float* w, const void* wm,
@@ -204,6 +217,14 @@ mcmg_status Ctx::plan_mfma() {
     mfma_pack_dims(dim, mode, cin, cout, bf, &op.cinp, &op.ncols, &op.npairs, &op.nsteps);
     op.on = false;
   };
+  // weight chunk: all K-steps at once when the LDS allows (one load latency
+  // per block), else halve until it fits
+  auto kchunk_for = [&](const MOp& op, int mt, int ntw) {
+    int kc = op.nsteps;
+    while (kc > 1 && mfma_lds_bytes(dim, bf, op.mode, mt, ntw, op.cinp, op.epi, kc) > 96 * 1024)
+      kc = (kc + 1) / 2;
+    return kc;
+  };
   // candidate tiles that fit, in a fixed preference order
   auto candidates = [&](const MOp& op) {
     std::vector<std::pair<int, int>> c;
@@ -211,7 +232,8 @@ mcmg_status Ctx::plan_mfma() {
     for (int mt : {2, 4, 1})
       for (int ntw : {1, 2, 4}) {
         if (nt % ntw) continue;
-        if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, op.cinp, op.epi) > lds_max) continue;
+        const int kc = kchunk_for(op, mt, ntw);
+        if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, op.cinp, op.epi, kc) > lds_max) continue;
         c.push_back({mt, ntw});
       }
     return c;
@@ -252,16 +274,19 @@ mcmg_status Ctx::plan_mfma() {
         for (auto& c : cands)
           if (c.first == it->second.first && c.second == it->second.second) {
             op.mt = c.first; op.ntw = c.second; op.on = true;
+            op.kchunk = kchunk_for(op, op.mt, op.ntw);
             return MCMG_OK;
           }
       }
     }
     op.mt = cands[0].first; op.ntw = cands[0].second; op.on = true;
+    op.kchunk = kchunk_for(op, op.mt, op.ntw);
     if (!tune || cands.size() == 1) return MCMG_OK;
     float best = 1e30f;
     std::pair<int, int> bc = cands[0];
     for (auto& c : cands) {
       op.mt = c.first; op.ntw = c.second;
+      op.kchunk = kchunk_for(op, op.mt, op.ntw);
       hipError_t e = launch();                      // warm-up
       if (e != hipSuccess) return fail(MCMG_E_HIP, "tune: %s", hipGetErrorString(e));
       if ((e = hipEventRecord(ev0, stream)) != hipSuccess) return fail(MCMG_E_HIP, "tune event");
@@ -274,6 +299,7 @@ mcmg_status Ctx::plan_mfma() {
       if (ms < best) { best = ms; bc = c; }
     }
     op.mt = bc.first; op.ntw = bc.second;
+    op.kchunk = kchunk_for(op, op.mt, op.ntw);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = bc;
     save_cache_locked();

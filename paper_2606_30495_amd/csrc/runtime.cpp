@@ -218,7 +218,7 @@ hipError_t Ctx::dispatch_conv(const ConvLaunch& a) {
   if (!prof.on) return launch_conv(a, stream);
   double fl, by;
   conv_work(a, &fl, &by);
-  return timed(conv_kernel_name(a), fl, by, [&] { return launch_conv(a, stream); });
+  return timed(conv_kernel_name(a), fl, by, [=] { return launch_conv(a, stream); });
 }
 
 // Alg. 2.  rin: complex field (tin = T_F64 or T_F32); zout: complex (tout).
@@ -300,9 +300,9 @@ hipError_t Ctx::level1(Level& lv, int var, int step) {
     const double P = (double)lv.dims.total, T = dim == 2 ? 9.0 : 27.0;
     const double fl = var == L1_RESID ? 2.0 * T * 4 * 2 * P : 2.0 * T * 4 * (var == L1_FIRST ? 2 : 4) * P;
     const double by = var == L1_RESID ? 32.0 * P : (var == L1_FIRST ? 24.0 * P : 40.0 * P);
-    static const char* nm[3] = {"l1_kernel<STEP>", "l1_kernel<FIRST>", "l1_kernel<RESID>"};
-    const char* name = intern_name(std::string(nm[var]) + (dim == 2 ? "2d" : "3d"));
-    e = timed(name, fl, by, [&] { return launch_level1(l, stream); });
+    const char* name = intern_name(std::string("l1_kernel<") + std::to_string(dim) + ", " +
+                                   std::to_string(var) + ">");
+    e = timed(name, fl, by, [=] { return launch_level1(l, stream); });
   }
   if (e == hipSuccess && var != L1_RESID) std::swap(lv.e, lv.e_alt);
   return e;
@@ -370,9 +370,9 @@ hipError_t Ctx::helm_timed(int tin, const void* u, const double* f, double* out,
   // algorithmic traffic: u, k^2 and the output (+ f in residual form)
   const double bytes = N * ((tin == T_F64 ? 16.0 : 8.0) + 8.0 + 16.0 + (f ? 16.0 : 0.0));
   const double flops = N * (dim == 2 ? 38.0 : 54.0);
-  const char* name = intern_name(std::string("helm_kernel<") + std::to_string(dim) + "," +
+  const char* name = intern_name(std::string("helm_kernel<") + std::to_string(dim) + ", " +
                                  (tin == T_F64 ? "double" : "float") + ">");
-  return timed(name, flops, bytes, [&] { return launch_helm(op, tin, u, f, out, partial, stream); });
+  return timed(name, flops, bytes, [=] { return launch_helm(op, tin, u, f, out, partial, stream); });
 }
 
 HelmOp Ctx::helm() const {
@@ -617,8 +617,36 @@ mcmg_status mcmg_prof_report(mcmg_handle h, char* buf, size_t cap) {
   out += "]";
   if (out.size() + 1 > cap) return fail(MCMG_E_ARG, "report buffer too small (%zu bytes needed)", out.size() + 1);
   memcpy(buf, out.c_str(), out.size() + 1);
-  c->prof.recs.clear();
-  c->prof.used = 0;
+  return MCMG_OK;
+}
+
+mcmg_status mcmg_prof_replay(mcmg_handle h, const char* name, int reps, double* avg_ms,
+                             int* launches) {
+  if (!h || !name || !avg_ms || reps < 1) return fail(MCMG_E_ARG, "bad argument");
+  Ctx* c = (Ctx*)h;
+  std::vector<const ProfRec*> sel;
+  for (const ProfRec& r : c->prof.recs)
+    if (std::string(r.name) == name) sel.push_back(&r);
+  if (sel.empty()) return fail(MCMG_E_ARG, "no recorded launch of %s", name);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(MCMG_E_HIP, "event create");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(MCMG_E_HIP, "event create"); }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+  for (int k = 0; k < reps && e == hipSuccess; ++k)
+    for (const ProfRec* r : sel) {
+      e = r->replay();
+      if (e != hipSuccess) break;
+    }
+  if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(MCMG_E_HIP, "replay: %s", hipGetErrorString(e));
+  *avg_ms = ms / ((double)sel.size() * reps);
+  if (launches) *launches = (int)sel.size() * reps;
   return MCMG_OK;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -17,7 +18,7 @@ mcmg_status fail(mcmg_status s, const char* fmt, ...);
 struct MOp {
   bool on = false;
   int mode = 0, epi = 0, cin = 0, cout = 0, cinp = 0, ncols = 0, npairs = 0, nsteps = 0;
-  int mt = 2, ntw = 1;
+  int mt = 2, ntw = 1, kchunk = 1;
   Dims in{}, out{};
 };
 
@@ -43,11 +44,14 @@ struct Level {
 };
 
 // Optional per-launch timing with HIP events on the handle's stream, with
-// the algorithmic work of every launch (flops, bytes) from its shapes.
+// the algorithmic work of every launch (flops, bytes) from its shapes.  Each
+// record keeps a by-value copy of its launch so that the launches of one
+// kernel can be replayed back to back between a single event pair.
 struct ProfRec {
   const char* name;
   double flops, bytes;
   hipEvent_t a, b;
+  std::function<hipError_t()> replay;
 };
 
 struct Prof {
@@ -105,8 +109,9 @@ struct Ctx {
   size_t device_bytes = 0;
   Prof prof;
 
+  // `launch` must capture by value: it is kept for replay.
   template <class F>
-  hipError_t timed(const char* name, double flops, double bytes, F&& launch) {
+  hipError_t timed(const char* name, double flops, double bytes, F launch) {
     if (!prof.on) return launch();
     hipEvent_t a = prof.get(), b = prof.get();
     if (!a || !b) return hipErrorOutOfMemory;
@@ -115,7 +120,7 @@ struct Ctx {
     e = launch();
     if (e != hipSuccess) return e;
     e = hipEventRecord(b, stream);
-    prof.recs.push_back({name, flops, bytes, a, b});
+    prof.recs.push_back({name, flops, bytes, a, b, std::function<hipError_t()>(launch)});
     return e;
   }
 

@@ -122,22 +122,39 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       // pass 0 (always) and pass 1 (device-gated re-orthogonalisation)
       const double vb = 16.0 * (double)N;
       HCK(c->timed("multidot_kernel", 8.0 * N * (nv + 1), vb * (nv + 1),
-                   [&] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, nullptr, s); }));
+                   [=] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, nullptr, s); }));
       HCK(launch_reduce_dots(c->partial, nb, nv, c->coef, Hcol, c->scal + 8, nullptr, s));
       HCK(c->timed("update_kernel", 8.0 * N * (nv + 1), vb * (nv + 2),
-                   [&] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, nullptr, s); }));
+                   [=] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, nullptr, s); }));
       HCK(launch_reduce_norm(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, 0,
                              c->ortho == 1, s));
-      HCK(c->timed("multidot_kernel(reorth)", 8.0 * N * (nv + 1), vb * (nv + 1),
-                   [&] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, c->skip, s); }));
+      // the second pass exits at once unless the device flagged cancellation
+      HCK(c->timed("multidot_kernel", 8.0 * N * (nv + 1), vb * (nv + 1),
+                   [=] { return launch_multidot(c->V, N, nv, c->wv, N, c->partial, c->skip, s); }));
       HCK(launch_reduce_dots(c->partial, nb, nv, c->coef, Hcol, c->scal + 10, c->skip, s));
-      HCK(c->timed("update_kernel(reorth)", 8.0 * N * (nv + 1), vb * (nv + 2),
-                   [&] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, c->skip, s); }));
+      HCK(c->timed("update_kernel", 8.0 * N * (nv + 1), vb * (nv + 2),
+                   [=] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, c->skip, s); }));
       HCK(launch_reduce_norm(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, 1, 0, s));
       HCK(launch_givens(c->H, ldh, j, c->scal + 9, c->cs, c->sn, c->g, c->scal + 16, s));
       if (j + 1 < m) HCK(launch_scale(c->wv, c->scal + 9, c->V + 2LL * (j + 1) * N, N, s));
       HCK(read_scal(c, 16, 3));
       const double rho = c->host_scal[0], hn = c->host_scal[1], cn = c->host_scal[2];
+      if (c->prof.on && c->prof.recs.size() >= 2) {
+        // the second Gram-Schmidt pass did no work when the device skipped it
+        int skipped = 0;
+        HCK(hipMemcpy(&skipped, c->skip, sizeof(int), hipMemcpyDeviceToHost));
+        if (skipped) {
+          int fixed = 0;
+          for (size_t q = c->prof.recs.size(); q-- > 0 && fixed < 2;) {
+            ProfRec& pr = c->prof.recs[q];
+            if (pr.name == std::string("multidot_kernel") || pr.name == std::string("update_kernel")) {
+              pr.flops = 0.0;
+              pr.bytes = 0.0;
+              ++fixed;
+            }
+          }
+        }
+      }
       fin.hist.push_back(rho / fnorm);
       fin.relres_est = rho / fnorm;
       k = j + 1;
@@ -147,7 +164,7 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
     }
     HCK(launch_backsolve(c->H, ldh, k, c->g, c->y, s));
     HCK(c->timed("zupdate_kernel", 8.0 * N * k, (8.0 * k + 32.0) * N,
-                 [&] { return launch_zupdate(c->Z, N, k, c->y, u, N, s); }));
+                 [=] { return launch_zupdate(c->Z, N, k, c->y, u, N, s); }));
     HCK(true_residual(c, f, u));
     HCK(read_scal(c, 3, 1));
     beta = c->host_scal[0];

@@ -1,0 +1,132 @@
+"""Summaries of rocprofv3 CSV output (kernel stats and PMC counters).
+
+    python3 -m paper_2606_30495_amd.profsum stats <kernel_stats.csv> [top]
+    python3 -m paper_2606_30495_amd.profsum traffic --fetch <dir> --write <dir>
+        --cal-fetch <dir> --cal-write <dir> --cal-bytes B --kernel NAME=SOURCE ...
+
+`traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
+name, scales each by the calibration copy kernel's bytes-moved / counter
+ratio and prints a Markdown summary with a JSON block
+{"kernels": {name: {bytes_per_launch, fetch_bytes, write_bytes, source,
+sha256}}} that bench.py reads (it ignores an entry whose source changed).
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+
+def short(name):
+    for p in ("void ", "mcmg::(anonymous namespace)::"):
+        name = name.replace(p, "")
+    name = re.sub(r"\(.*$", "", name)
+    return name.strip()
+
+
+def stats(path, top=30):
+    rows = list(csv.DictReader(open(path)))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    out.append(f"\ntotal kernel time {total / 1e6:.3f} ms over {sum(int(r['Calls']) for r in rows)} dispatches")
+    return "\n".join(out)
+
+
+def counter_means(d, counter):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    acc = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r.get("Counter_Name") != counter:
+                continue
+            k = short(r["Kernel_Name"])
+            acc.setdefault(k, []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}, {k: len(v) for k, v in acc.items()}
+
+
+def traffic(args):
+    kv = dict(a.split("=", 1) for a in args["kernel"])
+    fetch, nf = counter_means(args["fetch"], "FETCH_SIZE")
+    write, nw = counter_means(args["write"], "WRITE_SIZE")
+    cf, _ = counter_means(args["cal_fetch"], "FETCH_SIZE")
+    cw, _ = counter_means(args["cal_write"], "WRITE_SIZE")
+    cal_bytes = float(args["cal_bytes"])
+    ckf = max(cf.items(), key=lambda x: x[1])
+    ckw = max(cw.items(), key=lambda x: x[1])
+    sf = cal_bytes / (ckf[1] * 1024.0)
+    sw = cal_bytes / (ckw[1] * 1024.0)
+    lines = [f"copy calibration: `{ckf[0]}` moves {cal_bytes:.0f} B per launch; FETCH_SIZE reads "
+             f"{ckf[1]:.0f} KiB (scale {sf:.4f}), WRITE_SIZE reads {ckw[1]:.0f} KiB (scale {sw:.4f})", ""]
+    table = {"kernels": {}}
+    lines.append("| kernel | dispatches | FETCH KiB | WRITE KiB | scaled bytes/launch |")
+    lines.append("|---|---|---|---|---|")
+    for k in sorted(fetch, key=lambda x: -fetch[x] * nf[x])[:40]:
+        fb = fetch[k] * 1024.0 * sf
+        wb = write.get(k, 0.0) * 1024.0 * sw
+        lines.append(f"| `{k}` | {nf[k]} | {fetch[k]:.1f} | {write.get(k, 0.0):.1f} | {fb + wb:.4e} |")
+        if k in kv:
+            src = kv[k]
+            sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+            table["kernels"][k] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                                   "source": os.path.relpath(src), "sha256": sha}
+    lines.append("")
+    lines.append("```json")
+    lines.append(json.dumps(table, indent=1))
+    lines.append("```")
+    return "\n".join(lines)
+
+
+def replay_run(trace, kernel):
+    """Longest run of consecutive dispatches of `kernel` in a kernel trace
+    (the back-to-back replay bench.py issues for its dominant kernel):
+    dispatch count, mean kernel duration and mean start-to-start period."""
+    rows = list(csv.DictReader(open(trace)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    best, cur = [], []
+    for r in rows:
+        if short(r["Kernel_Name"]) == kernel:
+            cur.append(r)
+        else:
+            if len(cur) > len(best):
+                best = cur
+            cur = []
+    if len(cur) > len(best):
+        best = cur
+    if not best:
+        return f"no dispatch of `{kernel}`"
+    dur = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in best]
+    span = int(best[-1]["End_Timestamp"]) - int(best[0]["Start_Timestamp"])
+    return (f"`{kernel}`: longest back-to-back run {len(best)} dispatches, mean kernel duration "
+            f"{sum(dur) / len(dur) / 1e3:.3f} us, mean start-to-start {span / len(best) / 1e3:.3f} us")
+
+
+def main(argv):
+    if argv[0] == "replay":
+        print(replay_run(argv[1], argv[2]))
+        return
+    if argv[0] == "stats":
+        print(stats(argv[1], int(argv[2]) if len(argv) > 2 else 30))
+        return
+    if argv[0] == "traffic":
+        args = {"kernel": []}
+        i = 1
+        while i < len(argv):
+            key = argv[i].lstrip("-").replace("-", "_")
+            if key == "kernel":
+                args["kernel"].append(argv[i + 1])
+            else:
+                args[key] = argv[i + 1]
+            i += 2
+        print(traffic(args))
+        return
+    raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

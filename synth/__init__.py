@@ -24,8 +24,10 @@ from .configs import Config, CONFIGS, level_sides, ext_side
 from .media import (medium_bump, medium_grf, medium_ellipses, medium_layered_sphere,
                     omega_for_ppw, point_source, gaussian_source, random_rhs, make_problem)
 from .weights import make_weights, pack_blob, weight_names
+from .classical import shifted_laplacian
 
 __all__ = [
+    "shifted_laplacian",
     "Config", "CONFIGS", "level_sides", "ext_side",
     "medium_bump", "medium_grf", "medium_ellipses", "medium_layered_sphere",
     "omega_for_ppw", "point_source", "gaussian_source", "random_rhs", "make_problem",
