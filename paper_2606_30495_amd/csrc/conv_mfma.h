@@ -21,6 +21,26 @@ struct MfmaConv {
   Dims in, out;
 };
 
+// Per-problem kernel arguments (also the element of a batch table).
+struct MArgs {
+  const float* x;
+  const void* wA;
+  const void* wB;
+  float* y;
+  const float* r;
+  const float* feat;
+  int cin, cinp, cout, ncols, nsteps, npairs;
+  Dims in, out;
+  int tiles_x, tiles_y, tiles_z, kchunk;
+};
+
+// Arguments and block count of one problem's launch.
+MArgs mfma_args(const MfmaConv& a, int* nblk);
+// One launch over several problems that share every template parameter
+// (dim, precision, mode, epilogue, tile) and channel counts: b.tab holds a
+// device array of MArgs, b.pre the block prefix (np + 1 ints).
+hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b, hipStream_t s);
+
 // Padded sizes of the packed operands (see conv_mfma.hip for the layout).
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
                     int* npairs, int* nsteps);

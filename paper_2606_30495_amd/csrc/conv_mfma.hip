@@ -67,12 +67,20 @@ struct Geo {
 
 template <bool BF> constexpr int KVOF() { return BF ? 8 : 1; }
 
+// One block of the convolution: `vblk` is the block index inside this
+// problem's grid (the batched wrapper maps the launch's blocks onto problems).
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
-__global__ __launch_bounds__(256) void mconv_kernel(
-    const float* __restrict__ x, const void* __restrict__ wA, const void* __restrict__ wB,
-    float* __restrict__ y, const float* __restrict__ r, const float* __restrict__ feat, int cin,
-    int cinp, int cout, int ncols, int nsteps, int npairs, Dims in, Dims out, int tiles_x,
-    int tiles_y, int tiles_z, int kchunk) {
+__device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
+  const float* __restrict__ x = A.x;
+  const void* __restrict__ wA = A.wA;
+  const void* __restrict__ wB = A.wB;
+  float* __restrict__ y = A.y;
+  const float* __restrict__ r = A.r;
+  const float* __restrict__ feat = A.feat;
+  const int cin = A.cin, cinp = A.cinp, cout = A.cout, ncols = A.ncols, nsteps = A.nsteps;
+  const int npairs = A.npairs, tiles_x = A.tiles_x, tiles_y = A.tiles_y, tiles_z = A.tiles_z;
+  const int kchunk = A.kchunk;
+  const Dims in = A.in, out = A.out;
   using G = Geo<D, MODE, MT>;
   constexpr int KV = KVOF<BF>();
   constexpr int NACC = (EPI == EPI_RESID) ? 2 : 1;
@@ -84,7 +92,7 @@ __global__ __launch_bounds__(256) void mconv_kernel(
 
   const int ntiles = tiles_x * tiles_y * tiles_z;
   const int per = (ntiles + 7) / 8;
-  const int tl = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int tl = (vblk % 8) * per + vblk / 8;
   if (tl >= ntiles) return;
   const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, tz = tl / (tiles_x * tiles_y);
   const int x0 = tx * G::TX, y0 = ty * G::TY, z0 = tz * G::TZ;
@@ -271,62 +279,106 @@ __global__ __launch_bounds__(256) void mconv_kernel(
 }
 
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
-hipError_t run(const MfmaConv& a, hipStream_t s) {
-  using G = Geo<D, MODE, MT>;
-  // output tiles are taken over the GEMM row grid: S1 = output grid,
-  // S2 = coarse output grid, T2 = coarse (input) grid
-  const Dims& rows = (MODE == CONV_T2) ? a.in : a.out;
-  const int RX = (D == 2) ? rows.n[1] : rows.n[2], RY = (D == 2) ? rows.n[0] : rows.n[1];
-  const int RZ = (D == 2) ? 1 : rows.n[0];
-  const int tx = (RX + G::TX - 1) / G::TX, ty = (RY + G::TY - 1) / G::TY, tz = (RZ + G::TZ - 1) / G::TZ;
-  const int ntiles = tx * ty * tz;
-  const int nblk = ((ntiles + 7) / 8) * 8;
+__global__ __launch_bounds__(256) void mconv_kernel(MArgs A) {
+  mconv_body<D, BF, MODE, EPI, MT, NTW>(A, blockIdx.x);
+}
+
+// Batched form: one launch for several problems; pre[p] is the first block of
+// problem p (pre[np] = total blocks), tab[p] its arguments.
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
+__global__ __launch_bounds__(256) void mconv_kernel_batched(const MArgs* __restrict__ tab,
+                                                            const int* __restrict__ pre, int np,
+                                                            const int* __restrict__ frozen) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const MArgs A = tab[p];
+  mconv_body<D, BF, MODE, EPI, MT, NTW>(A, blockIdx.x - pre[p]);
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
+hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
   const int nslices = a.ncols / (16 * NTW);
-  hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW>), dim3(nblk, nslices), dim3(256),
-                     mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi, a.kchunk), s, a.x, a.wA,
-                     a.wB, a.y, a.r, a.feat, a.cin, a.cinp, a.cout, a.ncols, a.nsteps, a.npairs, a.in,
-                     a.out, tx, ty, tz, a.kchunk);
+  const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi, a.kchunk);
+  if (b) {
+    hipLaunchKernelGGL((mconv_kernel_batched<D, BF, MODE, EPI, MT, NTW>), dim3(b->total, nslices),
+                       dim3(256), lds, s, (const MArgs*)b->tab, b->pre, b->np, b->frozen);
+  } else {
+    int nblk;
+    const MArgs A = mfma_args(a, &nblk);
+    hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW>), dim3(nblk, nslices), dim3(256),
+                       lds, s, A);
+  }
   return hipGetLastError();
 }
 
 template <int D, bool BF, int MODE, int EPI, int MT>
-hipError_t by_ntw(const MfmaConv& a, hipStream_t s) {
+hipError_t by_ntw(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
   switch (a.ntw) {
-    case 1: return run<D, BF, MODE, EPI, MT, 1>(a, s);
-    case 2: return run<D, BF, MODE, EPI, MT, 2>(a, s);
-    case 4: return run<D, BF, MODE, EPI, MT, 4>(a, s);
+    case 1: return run<D, BF, MODE, EPI, MT, 1>(a, b, s);
+    case 2: return run<D, BF, MODE, EPI, MT, 2>(a, b, s);
+    case 4: return run<D, BF, MODE, EPI, MT, 4>(a, b, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int D, bool BF, int MODE, int EPI>
-hipError_t by_mt(const MfmaConv& a, hipStream_t s) {
+hipError_t by_mt(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
   switch (a.mt) {
-    case 1: return by_ntw<D, BF, MODE, EPI, 1>(a, s);
-    case 2: return by_ntw<D, BF, MODE, EPI, 2>(a, s);
-    case 4: return by_ntw<D, BF, MODE, EPI, 4>(a, s);
+    case 1: return by_ntw<D, BF, MODE, EPI, 1>(a, b, s);
+    case 2: return by_ntw<D, BF, MODE, EPI, 2>(a, b, s);
+    case 4: return by_ntw<D, BF, MODE, EPI, 4>(a, b, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int D, bool BF>
-hipError_t by_mode(const MfmaConv& a, hipStream_t s) {
+hipError_t by_mode(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
   if (a.mode == CONV_S1) {
     switch (a.epi) {
-      case EPI_SET: return by_mt<D, BF, CONV_S1, EPI_SET>(a, s);
-      case EPI_ADD: return by_mt<D, BF, CONV_S1, EPI_ADD>(a, s);
-      case EPI_MUL: return by_mt<D, BF, CONV_S1, EPI_MUL>(a, s);
-      case EPI_RESID: return by_mt<D, BF, CONV_S1, EPI_RESID>(a, s);
+      case EPI_SET: return by_mt<D, BF, CONV_S1, EPI_SET>(a, b, s);
+      case EPI_ADD: return by_mt<D, BF, CONV_S1, EPI_ADD>(a, b, s);
+      case EPI_MUL: return by_mt<D, BF, CONV_S1, EPI_MUL>(a, b, s);
+      case EPI_RESID: return by_mt<D, BF, CONV_S1, EPI_RESID>(a, b, s);
     }
   } else if (a.mode == CONV_S2 && a.epi == EPI_SET) {
-    return by_mt<D, BF, CONV_S2, EPI_SET>(a, s);
+    return by_mt<D, BF, CONV_S2, EPI_SET>(a, b, s);
   } else if (a.mode == CONV_T2 && a.epi == EPI_ADD) {
-    return by_mt<D, BF, CONV_T2, EPI_ADD>(a, s);
+    return by_mt<D, BF, CONV_T2, EPI_ADD>(a, b, s);
   }
   return hipErrorInvalidValue;
 }
 
+hipError_t dispatch(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  if (a.dim == 2) return a.bf16 ? by_mode<2, true>(a, b, s) : by_mode<2, false>(a, b, s);
+  if (a.dim == 3) return a.bf16 ? by_mode<3, true>(a, b, s) : by_mode<3, false>(a, b, s);
+  return hipErrorInvalidValue;
+}
+
 }  // namespace
+
+MArgs mfma_args(const MfmaConv& a, int* nblk) {
+  const int TX = 16 * a.mt, TY = a.dim == 2 ? 4 : 2, TZ = a.dim == 2 ? 1 : 2;
+  // output tiles are taken over the GEMM row grid: S1 = output grid,
+  // S2 = coarse output grid, T2 = coarse (input) grid
+  const Dims& rows = (a.mode == CONV_T2) ? a.in : a.out;
+  const int RX = (a.dim == 2) ? rows.n[1] : rows.n[2], RY = (a.dim == 2) ? rows.n[0] : rows.n[1];
+  const int RZ = (a.dim == 2) ? 1 : rows.n[0];
+  MArgs A;
+  A.x = a.x; A.wA = a.wA; A.wB = a.wB; A.y = a.y; A.r = a.r; A.feat = a.feat;
+  A.cin = a.cin; A.cinp = a.cinp; A.cout = a.cout; A.ncols = a.ncols; A.nsteps = a.nsteps;
+  A.npairs = a.npairs; A.in = a.in; A.out = a.out; A.kchunk = a.kchunk;
+  A.tiles_x = (RX + TX - 1) / TX;
+  A.tiles_y = (RY + TY - 1) / TY;
+  A.tiles_z = (RZ + TZ - 1) / TZ;
+  const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
+  *nblk = ((ntiles + 7) / 8) * 8;
+  return A;
+}
+
+hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b, hipStream_t s) {
+  if (b.np == 0 || b.total == 0) return hipSuccess;
+  return dispatch(proto, &b, s);
+}
 
 size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi, int kchunk) {
   const int TX = 16 * mt, TY = dim == 2 ? 4 : 2, TZ = dim == 2 ? 1 : 2;
@@ -353,9 +405,7 @@ void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, i
 
 hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s) {
   if (a.out.total == 0 || a.in.total == 0) return hipSuccess;
-  if (a.dim == 2) return a.bf16 ? by_mode<2, true>(a, s) : by_mode<2, false>(a, s);
-  if (a.dim == 3) return a.bf16 ? by_mode<3, true>(a, s) : by_mode<3, false>(a, s);
-  return hipErrorInvalidValue;
+  return dispatch(a, nullptr, s);
 }
 
 const char* mfma_kernel_name(const MfmaConv& a) {

@@ -4,14 +4,16 @@
 // blockIdx.y selects the chunk.  Weights are laid out [tap][cin][cpad] so
 // that the CT weights a thread needs for one (tap, cin) pair are contiguous
 // and wave-uniform (scalar loads).  Three sampling modes (Sec. 3.2):
-//   S1: stride 1, zero padding 1 (smoother and level operator convs, lift,
-//       projection, setup nets);
+//   S1: stride 1, zero padding 1 (lift, projection, setup nets, and solve
+//       convolutions on levels without a matrix-core plan);
 //   S2: stride 2, pad 1, ceil(n/2) outputs (restriction R, setup f_a);
 //   T2: transposed stride-2 (prolongation P), output forced to the fine size:
 //       coarse node X feeds fine node 2X + off.
 // Epilogues fuse the elementwise work of the V-cycle into the convolution:
 //   SET / ADD (e += W * u) / MUL (s (.) (K * t)) / GELU (setup) /
 //   RESID (t = r - W * e - a (.) (KA * e), two weight tensors at once).
+// The batched form runs the same convolution for several problems (own
+// pointers and grids) in one launch.
 #include <string>
 
 #include "internal.h"
@@ -30,11 +32,16 @@ __device__ __forceinline__ float gelu_f(float x) {
 }
 
 template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
-__global__ __launch_bounds__(256) void conv_direct(
-    const TIN* __restrict__ x, const float* __restrict__ w, const float* __restrict__ w2,
-    TOUT* __restrict__ y, const float* __restrict__ r, const float* __restrict__ feat,
-    int cin, int cout, int cpad, Dims in, Dims out) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void conv_body(const DArgs& A, const int vblk) {
+  const TIN* __restrict__ x = reinterpret_cast<const TIN*>(A.x);
+  const float* __restrict__ w = A.w;
+  const float* __restrict__ w2 = A.w2;
+  TOUT* __restrict__ y = reinterpret_cast<TOUT*>(A.y);
+  const float* __restrict__ r = A.r;
+  const float* __restrict__ feat = A.feat;
+  const int cin = A.cin, cout = A.cout, cpad = A.cpad;
+  const Dims in = A.in, out = A.out;
+  const long long p = (long long)vblk * blockDim.x + threadIdx.x;
   if (p >= out.total) return;
   const int chunk = blockIdx.y;
   int o[3];
@@ -99,40 +106,69 @@ __global__ __launch_bounds__(256) void conv_direct(
 }
 
 template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
-hipError_t run(const ConvLaunch& a, hipStream_t s) {
+__global__ __launch_bounds__(256) void conv_direct(DArgs A) {
+  conv_body<D, CT, MODE, EPI, TIN, TOUT>(A, blockIdx.x);
+}
+
+template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
+__global__ __launch_bounds__(256) void conv_direct_batched(const DArgs* __restrict__ tab,
+                                                           const int* __restrict__ pre, int np,
+                                                           const int* __restrict__ frozen) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const DArgs A = tab[p];
+  conv_body<D, CT, MODE, EPI, TIN, TOUT>(A, blockIdx.x - pre[p]);
+}
+
+template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
+hipError_t run(const ConvLaunch& a, const BatchLaunch* b, hipStream_t s) {
   const int nchunk = (a.cout + CT - 1) / CT;
-  dim3 grid((unsigned)((a.out.total + 255) / 256), (unsigned)nchunk);
-  hipLaunchKernelGGL((conv_direct<D, CT, MODE, EPI, TIN, TOUT>), grid, dim3(256), 0, s,
-                     (const TIN*)a.x, a.w, a.w2, (TOUT*)a.y, a.r, a.feat, a.cin, a.cout,
-                     a.cpad, a.in, a.out);
+  if (b) {
+    hipLaunchKernelGGL((conv_direct_batched<D, CT, MODE, EPI, TIN, TOUT>),
+                       dim3((unsigned)b->total, (unsigned)nchunk), dim3(256), 0, s,
+                       (const DArgs*)b->tab, b->pre, b->np, b->frozen);
+  } else {
+    int nblk;
+    const DArgs A = conv_args(a, &nblk);
+    hipLaunchKernelGGL((conv_direct<D, CT, MODE, EPI, TIN, TOUT>), dim3((unsigned)nblk, (unsigned)nchunk),
+                       dim3(256), 0, s, A);
+  }
   return hipGetLastError();
 }
 
 template <int D, int CT, int MODE>
-hipError_t by_epi(const ConvLaunch& a, hipStream_t s) {
+hipError_t by_epi(const ConvLaunch& a, const BatchLaunch* b, hipStream_t s) {
   if (a.tin == T_F32 && a.tout == T_F32) {
     switch (a.epi) {
-      case EPI_SET: return run<D, CT, MODE, EPI_SET, float, float>(a, s);
-      case EPI_ADD: return run<D, CT, MODE, EPI_ADD, float, float>(a, s);
-      case EPI_MUL: return run<D, CT, MODE, EPI_MUL, float, float>(a, s);
-      case EPI_GELU: return run<D, CT, MODE, EPI_GELU, float, float>(a, s);
-      case EPI_RESID: return run<D, CT, MODE, EPI_RESID, float, float>(a, s);
+      case EPI_SET: return run<D, CT, MODE, EPI_SET, float, float>(a, b, s);
+      case EPI_ADD: return run<D, CT, MODE, EPI_ADD, float, float>(a, b, s);
+      case EPI_MUL: return run<D, CT, MODE, EPI_MUL, float, float>(a, b, s);
+      case EPI_GELU: return run<D, CT, MODE, EPI_GELU, float, float>(a, b, s);
+      case EPI_RESID: return run<D, CT, MODE, EPI_RESID, float, float>(a, b, s);
     }
   }
   if (MODE == CONV_S1 && a.epi == EPI_SET) {
-    if (a.tin == T_F64 && a.tout == T_F32) return run<D, CT, MODE, EPI_SET, double, float>(a, s);
-    if (a.tin == T_F32 && a.tout == T_F64) return run<D, CT, MODE, EPI_SET, float, double>(a, s);
+    if (a.tin == T_F64 && a.tout == T_F32) return run<D, CT, MODE, EPI_SET, double, float>(a, b, s);
+    if (a.tin == T_F32 && a.tout == T_F64) return run<D, CT, MODE, EPI_SET, float, double>(a, b, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int D, int CT>
-hipError_t by_mode(const ConvLaunch& a, hipStream_t s) {
+hipError_t by_mode(const ConvLaunch& a, const BatchLaunch* b, hipStream_t s) {
   switch (a.mode) {
-    case CONV_S1: return by_epi<D, CT, CONV_S1>(a, s);
-    case CONV_S2: return by_epi<D, CT, CONV_S2>(a, s);
-    case CONV_T2: return by_epi<D, CT, CONV_T2>(a, s);
+    case CONV_S1: return by_epi<D, CT, CONV_S1>(a, b, s);
+    case CONV_S2: return by_epi<D, CT, CONV_S2>(a, b, s);
+    case CONV_T2: return by_epi<D, CT, CONV_T2>(a, b, s);
   }
+  return hipErrorInvalidValue;
+}
+
+hipError_t dispatch(const ConvLaunch& a, const BatchLaunch* b, hipStream_t s) {
+  const int ct = conv_chunk(a.cout);
+  if (a.cpad % ct != 0) return hipErrorInvalidValue;
+  if (a.dim == 2) return ct == 2 ? by_mode<2, 2>(a, b, s) : by_mode<2, 8>(a, b, s);
+  if (a.dim == 3) return ct == 2 ? by_mode<3, 2>(a, b, s) : by_mode<3, 8>(a, b, s);
   return hipErrorInvalidValue;
 }
 
@@ -140,13 +176,22 @@ hipError_t by_mode(const ConvLaunch& a, hipStream_t s) {
 
 int conv_chunk(int cout) { return cout <= 2 ? 2 : 8; }
 
+DArgs conv_args(const ConvLaunch& a, int* nblk) {
+  DArgs A;
+  A.x = a.x; A.w = a.w; A.w2 = a.w2; A.y = a.y; A.r = a.r; A.feat = a.feat;
+  A.cin = a.cin; A.cout = a.cout; A.cpad = a.cpad; A.in = a.in; A.out = a.out;
+  *nblk = (int)((a.out.total + 255) / 256);
+  return A;
+}
+
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s) {
   if (a.out.total == 0) return hipSuccess;
-  const int ct = conv_chunk(a.cout);
-  if (a.cpad % ct != 0) return hipErrorInvalidValue;
-  if (a.dim == 2) return ct == 2 ? by_mode<2, 2>(a, s) : by_mode<2, 8>(a, s);
-  if (a.dim == 3) return ct == 2 ? by_mode<3, 2>(a, s) : by_mode<3, 8>(a, s);
-  return hipErrorInvalidValue;
+  return dispatch(a, nullptr, s);
+}
+
+hipError_t launch_conv_batched(const ConvLaunch& proto, const BatchLaunch& b, hipStream_t s) {
+  if (b.np == 0 || b.total == 0) return hipSuccess;
+  return dispatch(proto, &b, s);
 }
 
 namespace {
@@ -176,10 +221,6 @@ hipError_t launch_zero_f64(double* p, long long n, hipStream_t s) {
   hipLaunchKernelGGL(zero_f64, dim3((unsigned)b), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
-
-}  // namespace mcmg
-
-namespace mcmg {
 
 const char* conv_kernel_name(const ConvLaunch& a) {
   // the demangled template form profilers print

@@ -39,15 +39,22 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 template <int D, typename TIN>
-__global__ __launch_bounds__(HB) void helm_kernel(
-    const TIN* __restrict__ u, const double* __restrict__ f, double* __restrict__ out,
-    const double* __restrict__ k2, const double* __restrict__ cm0, const double* __restrict__ cp0,
-    const double* __restrict__ cm1, const double* __restrict__ cp1,
-    const double* __restrict__ cm2, const double* __restrict__ cp2, Dims n,
-    double* __restrict__ partial) {
+__device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
+  const TIN* __restrict__ u = reinterpret_cast<const TIN*>(A.u);
+  const double* __restrict__ f = A.f;
+  double* __restrict__ out = A.out;
+  const double* __restrict__ k2 = A.op.k2;
+  const double* __restrict__ cm0 = A.op.cm[0];
+  const double* __restrict__ cp0 = A.op.cp[0];
+  const double* __restrict__ cm1 = A.op.cm[1];
+  const double* __restrict__ cp1 = A.op.cp[1];
+  const double* __restrict__ cm2 = A.op.cm[2] ? A.op.cm[2] : A.op.cm[0];
+  const double* __restrict__ cp2 = A.op.cp[2] ? A.op.cp[2] : A.op.cp[0];
+  const Dims n = A.op.ext;
+  double* __restrict__ partial = A.partial;
   __shared__ double sh[HB / 64];
   double nrm = 0.0;
-  const long long base = (long long)blockIdx.x * HB * HPT;
+  const long long base = (long long)vblk * HB * HPT;
   for (int q = 0; q < HPT; ++q) {
     const long long p = base + (long long)q * HB + threadIdx.x;
     if (p >= n.total) break;
@@ -89,8 +96,42 @@ __global__ __launch_bounds__(HB) void helm_kernel(
   }
   if (partial) {
     const double t = block_sum(nrm, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (threadIdx.x == 0) partial[vblk] = t;
   }
+}
+
+template <int D, typename TIN>
+__global__ __launch_bounds__(HB) void helm_kernel(HArgs A) {
+  helm_body<D, TIN>(A, blockIdx.x);
+}
+
+template <int D, typename TIN>
+__global__ __launch_bounds__(HB) void helm_kernel_batched(const HArgs* __restrict__ tab,
+                                                          const int* __restrict__ pre, int np,
+                                                          const int* __restrict__ frozen) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const HArgs A = tab[p];
+  helm_body<D, TIN>(A, blockIdx.x - pre[p]);
+}
+
+hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLaunch* b,
+                         hipStream_t s) {
+  // 2D grids use axes 0,1 (axis 2 has n = 1); the kernel indexes axis 2 as
+  // the fastest, so 2D data is addressed as n0 x n1 x 1.
+  if (b) {
+    const HArgs* t = (const HArgs*)b->tab;
+    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<2, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
+    else if (dim == 2) hipLaunchKernelGGL((helm_kernel_batched<2, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
+    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<3, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
+    else hipLaunchKernelGGL((helm_kernel_batched<3, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
+  } else {
+    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel<2, double>), dim3(nb), dim3(HB), 0, s, *A);
+    else if (dim == 2) hipLaunchKernelGGL((helm_kernel<2, float>), dim3(nb), dim3(HB), 0, s, *A);
+    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel<3, double>), dim3(nb), dim3(HB), 0, s, *A);
+    else hipLaunchKernelGGL((helm_kernel<3, float>), dim3(nb), dim3(HB), 0, s, *A);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -101,28 +142,13 @@ int helm_blocks(const HelmOp& op) {
 
 hipError_t launch_helm(const HelmOp& op, int tin, const void* u, const double* f, double* out,
                        double* partial, hipStream_t s) {
-  const int nb = helm_blocks(op);
-  // 2D grids use axes 0,1 (axis 2 has n = 1); the kernel indexes axis 2 as
-  // the fastest, so 2D data is addressed as n0 x n1 x 1.
-  Dims n = op.ext;
-  const double* cm2 = op.cm[2] ? op.cm[2] : op.cm[0];
-  const double* cp2 = op.cp[2] ? op.cp[2] : op.cp[0];
-  if (op.dim == 2) {
-    if (tin == T_F64)
-      hipLaunchKernelGGL((helm_kernel<2, double>), dim3(nb), dim3(HB), 0, s, (const double*)u, f,
-                         out, op.k2, op.cm[0], op.cp[0], op.cm[1], op.cp[1], cm2, cp2, n, partial);
-    else
-      hipLaunchKernelGGL((helm_kernel<2, float>), dim3(nb), dim3(HB), 0, s, (const float*)u, f,
-                         out, op.k2, op.cm[0], op.cp[0], op.cm[1], op.cp[1], cm2, cp2, n, partial);
-  } else {
-    if (tin == T_F64)
-      hipLaunchKernelGGL((helm_kernel<3, double>), dim3(nb), dim3(HB), 0, s, (const double*)u, f,
-                         out, op.k2, op.cm[0], op.cp[0], op.cm[1], op.cp[1], cm2, cp2, n, partial);
-    else
-      hipLaunchKernelGGL((helm_kernel<3, float>), dim3(nb), dim3(HB), 0, s, (const float*)u, f,
-                         out, op.k2, op.cm[0], op.cp[0], op.cm[1], op.cp[1], cm2, cp2, n, partial);
-  }
-  return hipGetLastError();
+  HArgs A{op, u, f, out, partial};
+  return helm_dispatch(op.dim, tin, &A, helm_blocks(op), nullptr, s);
+}
+
+hipError_t launch_helm_batched(int dim, int tin, const BatchLaunch& b, hipStream_t s) {
+  if (b.np == 0 || b.total == 0) return hipSuccess;
+  return helm_dispatch(dim, tin, nullptr, 0, &b, s);
 }
 
 // ---- setup --------------------------------------------------------------

@@ -95,7 +95,8 @@ hipError_t launch_pml_tables(int n_ext, int npml, double h, double sigma_max,
                              double* cm, double* cp, hipStream_t s);
 
 // ---- Krylov --------------------------------------------------------------
-int red_blocks(long long n);                        // partial-sum grid size
+__host__ __device__ int red_blocks(long long n);    // partial-sum grid size
+int elem_blocks(long long n);                       // one complex entry per thread
 // partial[i * nb + b] for i < nvec: sum conj(V_i) w over block b;
 // partial[nvec * nb + b]: sum |w|^2 (complex parts interleaved).
 hipError_t launch_multidot(const double* V, long long ldv, int nvec, const double* w,
@@ -135,6 +136,37 @@ hipError_t launch_axpy_f32(const float* z, double* u, long long n, hipStream_t s
 hipError_t launch_cast_f32_f64(const float* z, double* out, long long n, hipStream_t s);
 hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t s);
 
+// Per-problem FGMRES state for the batched kernels (one handle's buffers).
+struct KArgs {
+  double* V;          // (m+1) basis vectors, complex, stride N
+  float* Z;           // m preconditioned vectors, complex float32, stride N
+  double* w;          // Arnoldi work vector
+  double* r;          // residual
+  const double* f;    // right-hand side
+  double* u;          // solution (in/out)
+  double *H, *cs, *sn, *g, *y, *coef, *partial, *scal;
+  int* skip;
+  long long N;        // extended-grid nodes
+  int ldh;            // m + 1
+  int k;              // iterations of the current cycle (solution update)
+  int always_two;     // force the second Gram-Schmidt pass
+};
+enum {
+  KB_MULTIDOT, KB_REDUCE_DOTS, KB_UPDATE, KB_REDUCE_NORM, KB_GIVENS, KB_SCALE_R, KB_SCALE_W,
+  KB_CYCLE_INIT, KB_BACKSOLVE, KB_ZUPDATE, KB_REDUCE_SUM
+};
+struct KBatch {
+  const KArgs* tab;       // device table, np entries
+  int np;
+  const int* pre_red;     // block prefix for red_blocks(N) grids
+  int total_red;
+  const int* pre_elem;    // block prefix for elem_blocks(N) grids
+  int total_elem;
+  const int* frozen;      // device flags (may be null)
+  double* gather;         // device, 4 doubles per problem: (rho, h_{j+1,j}, |col|, |r|)
+};
+hipError_t kb_launch(int op, const KBatch& b, int nvec, int j, int pass, int m, hipStream_t s);
+
 }  // namespace mcmg
 
 namespace mcmg {
@@ -155,4 +187,75 @@ struct L1Launch {
   Dims n;
 };
 hipError_t launch_level1(const L1Launch& l, hipStream_t s);
+}  // namespace mcmg
+
+namespace mcmg {
+// ---- batched launches ------------------------------------------------------
+// A batched kernel runs several independent problems in one launch: tab is a
+// device array of per-problem argument structs, pre (np + 1 ints, device)
+// the prefix of per-problem block counts, total = pre[np]; frozen (np ints,
+// device, may be null) marks problems whose blocks return at once.
+struct BatchLaunch {
+  const void* tab;
+  const int* pre;
+  int np;
+  int total;
+  const int* frozen;
+};
+
+// Problem of launch block b: the last p with pre[p] <= b (pre is ascending;
+// every lane takes the same path, so the loads are wave-uniform).
+__device__ __forceinline__ int batch_find(const int* __restrict__ pre, int np, int b) {
+  int lo = 0, hi = np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+}  // namespace mcmg
+
+namespace mcmg {
+// Per-problem arguments of the fused C = 2 sweep (element of a batch table;
+// wp points to device-resident weights).
+struct L1Args {
+  const float* e;
+  float* eo;
+  const float *r, *a, *s;
+  const L1Weights* wp;
+  Dims n;
+  int tiles_x, tiles_y, tiles_z;
+};
+L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk);
+hipError_t launch_level1_batched(int dim, int var, const BatchLaunch& b, hipStream_t s);
+}  // namespace mcmg
+
+namespace mcmg {
+// Per-problem arguments of the VALU direct convolution (batch table element).
+struct DArgs {
+  const void* x;
+  const float* w;
+  const float* w2;
+  void* y;
+  const float* r;
+  const float* feat;
+  int cin, cout, cpad;
+  Dims in, out;
+};
+DArgs conv_args(const ConvLaunch& a, int* nblk);
+hipError_t launch_conv_batched(const ConvLaunch& proto, const BatchLaunch& b, hipStream_t s);
+}  // namespace mcmg
+
+namespace mcmg {
+// Per-problem arguments of the Helmholtz operator (batch table element):
+// out = A u, or out = f - A u with per-block |out|^2 partials.
+struct HArgs {
+  HelmOp op;
+  const void* u;
+  const double* f;
+  double* out;
+  double* partial;
+};
+hipError_t launch_helm_batched(int dim, int tin, const BatchLaunch& b, hipStream_t s);
 }  // namespace mcmg

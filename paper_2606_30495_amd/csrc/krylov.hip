@@ -7,7 +7,12 @@
 // below 1/sqrt(2) of its value before the pass (the device sets a skip flag
 // that the second pass's kernels read, so the host never waits for it).
 // All reductions are fixed-order (per-block partials, then one block per
-// output), so results are bitwise reproducible run to run.
+// output), so results are bitwise reproducible run to run and do not depend
+// on which other problems share a batched launch.
+//
+// Every kernel is a device body shared by a single-problem launcher and a
+// batched one (one launch for many problems, per-problem arguments from a
+// KArgs table; problems flagged in `frozen` return at once).
 #include "internal.h"
 
 namespace mcmg {
@@ -35,14 +40,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-__global__ __launch_bounds__(RB) void multidot_kernel(const double* __restrict__ V, long long ldv,
-                                                      int nvec, const double* __restrict__ w,
-                                                      long long n, double* __restrict__ partial,
-                                                      const int* __restrict__ skip) {
-  if (skip && skip[0]) return;
+__device__ __forceinline__ void multidot_body(const double* __restrict__ V, long long ldv, int nvec,
+                                              const double* __restrict__ w, long long n,
+                                              double* __restrict__ partial, int nb, int vblk) {
   __shared__ double sh[RB / 64];
-  const int nb = gridDim.x;
-  const long long base = (long long)blockIdx.x * RB * RPT;
+  const long long base = (long long)vblk * RB * RPT;
   double wr[RPT], wi[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -66,8 +68,8 @@ __global__ __launch_bounds__(RB) void multidot_kernel(const double* __restrict__
     const double tr = block_sum(sr, sh);
     const double ti = block_sum(si, sh);
     if (threadIdx.x == 0) {
-      partial[2 * ((long long)i * nb + blockIdx.x)] = tr;
-      partial[2 * ((long long)i * nb + blockIdx.x) + 1] = ti;
+      partial[2 * ((long long)i * nb + vblk)] = tr;
+      partial[2 * ((long long)i * nb + vblk) + 1] = ti;
     }
   }
   double s2 = 0.0;
@@ -75,20 +77,16 @@ __global__ __launch_bounds__(RB) void multidot_kernel(const double* __restrict__
   for (int q = 0; q < RPT; ++q) s2 += wr[q] * wr[q] + wi[q] * wi[q];
   const double t2 = block_sum(s2, sh);
   if (threadIdx.x == 0) {
-    partial[2 * ((long long)nvec * nb + blockIdx.x)] = t2;
-    partial[2 * ((long long)nvec * nb + blockIdx.x) + 1] = 0.0;
+    partial[2 * ((long long)nvec * nb + vblk)] = t2;
+    partial[2 * ((long long)nvec * nb + vblk) + 1] = 0.0;
   }
 }
 
-// One block per output: fixed-order tree reduction of nb complex partials.
-__global__ __launch_bounds__(RB) void reduce_dots_kernel(const double* __restrict__ partial, int nb,
-                                                         int nvec, double* __restrict__ coef,
-                                                         double* __restrict__ Hcol,
-                                                         double* __restrict__ wnorm2,
-                                                         const int* __restrict__ skip) {
-  if (skip && skip[0]) return;
+// Output i of the dot reduction (i == nvec: |w|^2), fixed-order tree.
+__device__ __forceinline__ void reduce_dots_body(const double* __restrict__ partial, int nb, int nvec,
+                                                 double* __restrict__ coef, double* __restrict__ Hcol,
+                                                 double* __restrict__ wnorm2, int i) {
   __shared__ double sh[RB / 64];
-  const int i = blockIdx.x;     // 0..nvec (nvec = |w|^2)
   double sr = 0.0, si = 0.0;
   for (int b = threadIdx.x; b < nb; b += RB) {
     sr += partial[2 * ((long long)i * nb + b)];
@@ -108,14 +106,11 @@ __global__ __launch_bounds__(RB) void reduce_dots_kernel(const double* __restric
   }
 }
 
-__global__ __launch_bounds__(RB) void update_kernel(const double* __restrict__ V, long long ldv,
-                                                    int nvec, const double* __restrict__ coef,
-                                                    double* __restrict__ w, long long n,
-                                                    double* __restrict__ partial,
-                                                    const int* __restrict__ skip) {
-  if (skip && skip[0]) return;
+__device__ __forceinline__ void update_body(const double* __restrict__ V, long long ldv, int nvec,
+                                            const double* __restrict__ coef, double* __restrict__ w,
+                                            long long n, double* __restrict__ partial, int vblk) {
   __shared__ double sh[RB / 64];
-  const long long base = (long long)blockIdx.x * RB * RPT;
+  const long long base = (long long)vblk * RB * RPT;
   double s2 = 0.0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -134,14 +129,13 @@ __global__ __launch_bounds__(RB) void update_kernel(const double* __restrict__ V
     s2 += ar * ar + ai * ai;
   }
   const double t = block_sum(s2, sh);
-  if (threadIdx.x == 0) partial[blockIdx.x] = t;
+  if (threadIdx.x == 0) partial[vblk] = t;
 }
 
-__global__ __launch_bounds__(RB) void reduce_norm_kernel(const double* __restrict__ partial, int nb,
-                                                         const double* __restrict__ wnorm2,
-                                                         double* __restrict__ hn, int* skip,
-                                                         int pass, int always_two) {
-  if (pass == 1 && skip[0]) return;
+__device__ __forceinline__ void reduce_norm_body(const double* __restrict__ partial, int nb,
+                                                 const double* __restrict__ wnorm2,
+                                                 double* __restrict__ hn, int* skip, int pass,
+                                                 int always_two) {
   __shared__ double sh[RB / 64];
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += RB) s += partial[b];
@@ -158,27 +152,9 @@ __global__ __launch_bounds__(RB) void reduce_norm_kernel(const double* __restric
   }
 }
 
-__global__ void scale_kernel(const double* __restrict__ w, const double* __restrict__ hn,
-                             double* __restrict__ v, long long n) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const double inv = 1.0 / hn[0];
-  v[2 * p] = w[2 * p] * inv;
-  v[2 * p + 1] = w[2 * p + 1] * inv;
-}
-
-__global__ void init_g_kernel(double* g, int m1, const double* beta) {
-  const int i = threadIdx.x;
-  if (i < m1) {
-    g[2 * i] = (i == 0) ? beta[0] : 0.0;
-    g[2 * i + 1] = 0.0;
-  }
-}
-
-// Single-thread Givens step on column j (complex, column-major, ldh rows).
-__global__ void givens_kernel(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
-                              double* g, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Givens step on column j of H (complex, column-major, ldh rows).
+__device__ __forceinline__ void givens_body(double* H, int ldh, int j, const double* hn, double* cs,
+                                            double* sn, double* g, double* out) {
   double* col = H + 2LL * j * ldh;
   const double b = hn[0];
   col[2 * (j + 1)] = b;
@@ -224,8 +200,8 @@ __global__ void givens_kernel(double* H, int ldh, int j, const double* hn, doubl
   out[2] = cn;
 }
 
-__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void backsolve_body(const double* H, int ldh, int k, const double* g,
+                                               double* y) {
   for (int i = k - 1; i >= 0; --i) {
     double sr = g[2 * i], si = g[2 * i + 1];
     for (int l = i + 1; l < k; ++l) {
@@ -240,10 +216,9 @@ __global__ void backsolve_kernel(const double* H, int ldh, int k, const double* 
   }
 }
 
-__global__ __launch_bounds__(RB) void zupdate_kernel(const float* __restrict__ Z, long long ldz,
-                                                     int k, const double* __restrict__ y,
-                                                     double* __restrict__ u, long long n) {
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void zupdate_body(const float* __restrict__ Z, long long ldz, int k,
+                                             const double* __restrict__ y, double* __restrict__ u,
+                                             long long n, long long p) {
   if (p >= n) return;
   double ar = u[2 * p], ai = u[2 * p + 1];
   for (int i = 0; i < k; ++i) {
@@ -257,13 +232,88 @@ __global__ __launch_bounds__(RB) void zupdate_kernel(const float* __restrict__ Z
   u[2 * p + 1] = ai;
 }
 
-__global__ __launch_bounds__(RB) void reduce_sum_kernel(const double* __restrict__ partial, int nb,
-                                                        double* __restrict__ out) {
+__device__ __forceinline__ void reduce_sum_body(const double* __restrict__ partial, int nb,
+                                                double* __restrict__ out) {
   __shared__ double sh[RB / 64];
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += RB) s += partial[b];
   const double t = block_sum(s, sh);
   if (threadIdx.x == 0) { out[0] = t; out[1] = sqrt(t); }
+}
+
+// ---- single-problem kernels -------------------------------------------------
+
+__global__ __launch_bounds__(RB) void multidot_kernel(const double* __restrict__ V, long long ldv,
+                                                      int nvec, const double* __restrict__ w,
+                                                      long long n, double* __restrict__ partial,
+                                                      const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  multidot_body(V, ldv, nvec, w, n, partial, gridDim.x, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RB) void reduce_dots_kernel(const double* __restrict__ partial, int nb,
+                                                         int nvec, double* __restrict__ coef,
+                                                         double* __restrict__ Hcol,
+                                                         double* __restrict__ wnorm2,
+                                                         const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  reduce_dots_body(partial, nb, nvec, coef, Hcol, wnorm2, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RB) void update_kernel(const double* __restrict__ V, long long ldv,
+                                                    int nvec, const double* __restrict__ coef,
+                                                    double* __restrict__ w, long long n,
+                                                    double* __restrict__ partial,
+                                                    const int* __restrict__ skip) {
+  if (skip && skip[0]) return;
+  update_body(V, ldv, nvec, coef, w, n, partial, blockIdx.x);
+}
+
+__global__ __launch_bounds__(RB) void reduce_norm_kernel(const double* __restrict__ partial, int nb,
+                                                         const double* __restrict__ wnorm2,
+                                                         double* __restrict__ hn, int* skip,
+                                                         int pass, int always_two) {
+  if (pass == 1 && skip[0]) return;
+  reduce_norm_body(partial, nb, wnorm2, hn, skip, pass, always_two);
+}
+
+__global__ void scale_kernel(const double* __restrict__ w, const double* __restrict__ hn,
+                             double* __restrict__ v, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const double inv = 1.0 / hn[0];
+  v[2 * p] = w[2 * p] * inv;
+  v[2 * p + 1] = w[2 * p + 1] * inv;
+}
+
+__global__ void init_g_kernel(double* g, int m1, const double* beta) {
+  const int i = threadIdx.x;
+  if (i < m1) {
+    g[2 * i] = (i == 0) ? beta[0] : 0.0;
+    g[2 * i + 1] = 0.0;
+  }
+}
+
+__global__ void givens_kernel(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
+                              double* g, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  givens_body(H, ldh, j, hn, cs, sn, g, out);
+}
+
+__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  backsolve_body(H, ldh, k, g, y);
+}
+
+__global__ __launch_bounds__(RB) void zupdate_kernel(const float* __restrict__ Z, long long ldz,
+                                                     int k, const double* __restrict__ y,
+                                                     double* __restrict__ u, long long n) {
+  zupdate_body(Z, ldz, k, y, u, n, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(RB) void reduce_sum_kernel(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+  reduce_sum_body(partial, nb, out);
 }
 
 __global__ void axpy_f32_kernel(const float* __restrict__ z, double* __restrict__ u, long long n) {
@@ -284,11 +334,124 @@ __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b
   b[p] = a[p];
 }
 
+// ---- batched kernels ---------------------------------------------------------
+// pre: per-problem block prefix; frozen: per-problem skip flag (may be null).
+
+__device__ __forceinline__ bool is_frozen(const int* frozen, int p) { return frozen && frozen[p]; }
+
+__global__ __launch_bounds__(RB) void kb_multidot(const KArgs* __restrict__ tab,
+                                                  const int* __restrict__ pre, int np,
+                                                  const int* __restrict__ frozen, int nvec, int pass) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  if (pass == 1 && A.skip[0]) return;
+  multidot_body(A.V, A.N, nvec, A.w, A.N, A.partial, red_blocks(A.N), blockIdx.x - pre[p]);
+}
+
+__global__ __launch_bounds__(RB) void kb_reduce_dots(const KArgs* __restrict__ tab,
+                                                     const int* __restrict__ frozen, int nvec, int j,
+                                                     int pass) {
+  const int p = blockIdx.y;
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  if (pass == 1 && A.skip[0]) return;
+  reduce_dots_body(A.partial, red_blocks(A.N), nvec, A.coef, A.H + 2LL * j * A.ldh,
+                   A.scal + (pass == 0 ? 8 : 10), blockIdx.x);
+}
+
+__global__ __launch_bounds__(RB) void kb_update(const KArgs* __restrict__ tab,
+                                                const int* __restrict__ pre, int np,
+                                                const int* __restrict__ frozen, int nvec, int pass) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  if (pass == 1 && A.skip[0]) return;
+  update_body(A.V, A.N, nvec, A.coef, A.w, A.N, A.partial, blockIdx.x - pre[p]);
+}
+
+__global__ __launch_bounds__(RB) void kb_reduce_norm(const KArgs* __restrict__ tab,
+                                                     const int* __restrict__ frozen, int pass) {
+  const int p = blockIdx.x;
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  if (pass == 1 && A.skip[0]) return;
+  reduce_norm_body(A.partial, red_blocks(A.N), A.scal + 8, A.scal + 9, A.skip, pass,
+                   pass == 0 ? A.always_two : 0);
+}
+
+__global__ void kb_givens(const KArgs* __restrict__ tab, const int* __restrict__ frozen, int j,
+                          double* __restrict__ gather) {
+  const int p = blockIdx.x;
+  if (threadIdx.x != 0 || is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  givens_body(A.H, A.ldh, j, A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
+  gather[4 * p + 0] = A.scal[16];
+  gather[4 * p + 1] = A.scal[17];
+  gather[4 * p + 2] = A.scal[18];
+}
+
+// mode 0: V_0 = r / |r|  (|r| in scal[3]);  mode 1: V_{j+1} = w / h_{j+1,j}
+__global__ __launch_bounds__(RB) void kb_scale(const KArgs* __restrict__ tab,
+                                               const int* __restrict__ pre, int np,
+                                               const int* __restrict__ frozen, int mode, int j) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  const long long q = (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x;
+  if (q >= A.N) return;
+  const double* src = mode == 0 ? A.r : A.w;
+  double* dst = A.V + (mode == 0 ? 0LL : 2LL * (j + 1) * A.N);
+  const double inv = 1.0 / (mode == 0 ? A.scal[3] : A.scal[9]);
+  dst[2 * q] = src[2 * q] * inv;
+  dst[2 * q + 1] = src[2 * q + 1] * inv;
+}
+
+// cycle start: H = 0, g = (|r|, 0, ...)
+__global__ __launch_bounds__(RB) void kb_cycle_init(const KArgs* __restrict__ tab,
+                                                    const int* __restrict__ frozen, int m) {
+  const int p = blockIdx.x;
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  const int nh = 2 * A.ldh * m;
+  for (int i = threadIdx.x; i < nh; i += RB) A.H[i] = 0.0;
+  for (int i = threadIdx.x; i < 2 * (m + 1); i += RB) A.g[i] = (i == 0) ? A.scal[3] : 0.0;
+}
+
+__global__ void kb_backsolve(const KArgs* __restrict__ tab) {
+  const int p = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  const KArgs& A = tab[p];
+  if (A.k > 0) backsolve_body(A.H, A.ldh, A.k, A.g, A.y);
+}
+
+__global__ __launch_bounds__(RB) void kb_zupdate(const KArgs* __restrict__ tab,
+                                                 const int* __restrict__ pre, int np) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  const KArgs& A = tab[p];
+  if (A.k <= 0) return;
+  zupdate_body(A.Z, A.N, A.k, A.y, A.u, A.N, (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x);
+}
+
+// |f - A u| after the batched residual kernel: scal[2] = |r|^2, scal[3] = |r|
+__global__ __launch_bounds__(RB) void kb_reduce_sum(const KArgs* __restrict__ tab,
+                                                    const int* __restrict__ frozen,
+                                                    double* __restrict__ gather) {
+  const int p = blockIdx.x;
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  reduce_sum_body(A.partial, red_blocks(A.N), A.scal + 2);
+  if (threadIdx.x == 0) gather[4 * p + 3] = A.scal[3];
+}
+
 inline unsigned nblk(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
 
-int red_blocks(long long n) { return (int)((n + (long long)RB * RPT - 1) / ((long long)RB * RPT)); }
+__host__ __device__ int red_blocks(long long n) {
+  return (int)((n + (long long)RB * RPT - 1) / ((long long)RB * RPT));
+}
+int elem_blocks(long long n) { return (int)((n + RB - 1) / RB); }
 
 hipError_t launch_multidot(const double* V, long long ldv, int nvec, const double* w, long long n,
                            double* partial, const int* skip, hipStream_t s) {
@@ -363,6 +526,55 @@ hipError_t launch_cast_f32_f64(const float* z, double* out, long long n, hipStre
 
 hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(nblk(2 * n, 256)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+// ---- batched launchers ------------------------------------------------------
+
+hipError_t kb_launch(int op, const KBatch& b, int nvec, int j, int pass, int m, hipStream_t s) {
+  if (b.np == 0) return hipSuccess;
+  switch (op) {
+    case KB_MULTIDOT:
+      hipLaunchKernelGGL(kb_multidot, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red, b.np,
+                         b.frozen, nvec, pass);
+      break;
+    case KB_REDUCE_DOTS:
+      hipLaunchKernelGGL(kb_reduce_dots, dim3(nvec + 1, b.np), dim3(RB), 0, s, b.tab, b.frozen,
+                         nvec, j, pass);
+      break;
+    case KB_UPDATE:
+      hipLaunchKernelGGL(kb_update, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red, b.np,
+                         b.frozen, nvec, pass);
+      break;
+    case KB_REDUCE_NORM:
+      hipLaunchKernelGGL(kb_reduce_norm, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, pass);
+      break;
+    case KB_GIVENS:
+      hipLaunchKernelGGL(kb_givens, dim3(b.np), dim3(64), 0, s, b.tab, b.frozen, j, b.gather);
+      break;
+    case KB_SCALE_R:
+      hipLaunchKernelGGL(kb_scale, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,
+                         b.frozen, 0, j);
+      break;
+    case KB_SCALE_W:
+      hipLaunchKernelGGL(kb_scale, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,
+                         b.frozen, 1, j);
+      break;
+    case KB_CYCLE_INIT:
+      hipLaunchKernelGGL(kb_cycle_init, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, m);
+      break;
+    case KB_BACKSOLVE:
+      hipLaunchKernelGGL(kb_backsolve, dim3(b.np), dim3(64), 0, s, b.tab);
+      break;
+    case KB_ZUPDATE:
+      hipLaunchKernelGGL(kb_zupdate, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np);
+      break;
+    case KB_REDUCE_SUM:
+      hipLaunchKernelGGL(kb_reduce_sum, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, b.gather);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

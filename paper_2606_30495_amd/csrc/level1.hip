@@ -32,10 +32,14 @@ template <> struct G1<3> { static constexpr int TZ = 2, TY = 4, TX = 32; };
 constexpr int NTH = 256;
 
 template <int D, int VAR>
-__global__ __launch_bounds__(NTH) void l1_kernel(const float2* __restrict__ e, float2* __restrict__ eo,
-                                                 const float2* __restrict__ r, const float2* __restrict__ a,
-                                                 const float2* __restrict__ s, L1Weights w, Dims n,
-                                                 int tiles_x, int tiles_y, int tiles_z) {
+__device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, const int vblk) {
+  const float2* __restrict__ e = reinterpret_cast<const float2*>(A.e);
+  float2* __restrict__ eo = reinterpret_cast<float2*>(A.eo);
+  const float2* __restrict__ r = reinterpret_cast<const float2*>(A.r);
+  const float2* __restrict__ a = reinterpret_cast<const float2*>(A.a);
+  const float2* __restrict__ s = reinterpret_cast<const float2*>(A.s);
+  const Dims n = A.n;
+  const int tiles_x = A.tiles_x, tiles_y = A.tiles_y, tiles_z = A.tiles_z;
   using G = G1<D>;
   constexpr int T = (D == 2) ? 9 : 27;
   constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // halo of the staged e
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(NTH) void l1_kernel(const float2* __restrict__ e, f
   const int NZ = (D == 2) ? 1 : n.n[0];
   const int ntiles = tiles_x * tiles_y * tiles_z;
   const int per = (ntiles + 7) / 8;
-  const int tl = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-contiguous bands
+  const int tl = (vblk % 8) * per + vblk / 8;   // XCD-contiguous bands
   if (tl >= ntiles) return;
   const int x0 = (tl % tiles_x) * G::TX, y0 = ((tl / tiles_x) % tiles_y) * G::TY;
   const int z0 = (tl / (tiles_x * tiles_y)) * G::TZ;
@@ -222,36 +226,79 @@ __global__ __launch_bounds__(NTH) void l1_kernel(const float2* __restrict__ e, f
 }
 
 template <int D, int VAR>
-hipError_t run(const L1Launch& l, hipStream_t s) {
-  using G = G1<D>;
-  const int NX = (D == 2) ? l.n.n[1] : l.n.n[2], NY = (D == 2) ? l.n.n[0] : l.n.n[1];
-  const int NZ = (D == 2) ? 1 : l.n.n[0];
-  const int tx = (NX + G::TX - 1) / G::TX, ty = (NY + G::TY - 1) / G::TY, tz = (NZ + G::TZ - 1) / G::TZ;
-  const int nt = tx * ty * tz;
-  hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(((nt + 7) / 8) * 8), dim3(NTH), 0, s,
-                     (const float2*)l.e, (float2*)l.eo, (const float2*)l.r, (const float2*)l.a,
-                     (const float2*)l.s, l.w, l.n, tx, ty, tz);
+__global__ __launch_bounds__(NTH) void l1_kernel(L1Args A, L1Weights w) {
+  l1_body<D, VAR>(A, w, blockIdx.x);
+}
+
+// Batched form: tab[p] per problem (weights through A.wp), pre = block prefix.
+template <int D, int VAR>
+__global__ __launch_bounds__(NTH) void l1_kernel_batched(const L1Args* __restrict__ tab,
+                                                         const int* __restrict__ pre, int np,
+                                                         const int* __restrict__ frozen) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const L1Args A = tab[p];
+  l1_body<D, VAR>(A, *A.wp, blockIdx.x - pre[p]);
+}
+
+template <int D, int VAR>
+hipError_t run(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
+  if (b) {
+    hipLaunchKernelGGL((l1_kernel_batched<D, VAR>), dim3(b->total), dim3(NTH), 0, s,
+                       (const L1Args*)b->tab, b->pre, b->np, b->frozen);
+  } else {
+    int nblk;
+    const L1Args A = l1_args(l, nullptr, &nblk);
+    hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(nblk), dim3(NTH), 0, s, A, l.w);
+  }
   return hipGetLastError();
+}
+
+hipError_t dispatch(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
+  if (l.dim == 2) {
+    switch (l.var) {
+      case L1_STEP: return run<2, L1_STEP>(l, b, s);
+      case L1_FIRST: return run<2, L1_FIRST>(l, b, s);
+      case L1_RESID: return run<2, L1_RESID>(l, b, s);
+    }
+  } else if (l.dim == 3) {
+    switch (l.var) {
+      case L1_STEP: return run<3, L1_STEP>(l, b, s);
+      case L1_FIRST: return run<3, L1_FIRST>(l, b, s);
+      case L1_RESID: return run<3, L1_RESID>(l, b, s);
+    }
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
 
+L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk) {
+  const int TX = l.dim == 2 ? G1<2>::TX : G1<3>::TX, TY = l.dim == 2 ? G1<2>::TY : G1<3>::TY;
+  const int TZ = l.dim == 2 ? G1<2>::TZ : G1<3>::TZ;
+  const int NX = (l.dim == 2) ? l.n.n[1] : l.n.n[2], NY = (l.dim == 2) ? l.n.n[0] : l.n.n[1];
+  const int NZ = (l.dim == 2) ? 1 : l.n.n[0];
+  L1Args A;
+  A.e = l.e; A.eo = l.eo; A.r = l.r; A.a = l.a; A.s = l.s; A.wp = wdev; A.n = l.n;
+  A.tiles_x = (NX + TX - 1) / TX;
+  A.tiles_y = (NY + TY - 1) / TY;
+  A.tiles_z = (NZ + TZ - 1) / TZ;
+  const int nt = A.tiles_x * A.tiles_y * A.tiles_z;
+  *nblk = ((nt + 7) / 8) * 8;
+  return A;
+}
+
 hipError_t launch_level1(const L1Launch& l, hipStream_t s) {
   if (l.n.total == 0) return hipSuccess;
-  if (l.dim == 2) {
-    switch (l.var) {
-      case L1_STEP: return run<2, L1_STEP>(l, s);
-      case L1_FIRST: return run<2, L1_FIRST>(l, s);
-      case L1_RESID: return run<2, L1_RESID>(l, s);
-    }
-  } else if (l.dim == 3) {
-    switch (l.var) {
-      case L1_STEP: return run<3, L1_STEP>(l, s);
-      case L1_FIRST: return run<3, L1_FIRST>(l, s);
-      case L1_RESID: return run<3, L1_RESID>(l, s);
-    }
-  }
-  return hipErrorInvalidValue;
+  return dispatch(l, nullptr, s);
+}
+
+hipError_t launch_level1_batched(int dim, int var, const BatchLaunch& b, hipStream_t s) {
+  if (b.np == 0 || b.total == 0) return hipSuccess;
+  L1Launch proto;
+  proto.dim = dim;
+  proto.var = var;
+  return dispatch(proto, &b, s);
 }
 
 }  // namespace mcmg

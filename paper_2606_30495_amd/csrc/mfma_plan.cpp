@@ -151,6 +151,13 @@ hipError_t Ctx::run_mop(const MOp& op, const float* x, const void* wA, const voi
   a.cin = op.cin; a.cinp = op.cinp; a.cout = op.cout; a.ncols = op.ncols;
   a.nsteps = op.nsteps; a.npairs = op.npairs;
   a.in = op.in; a.out = op.out;
+  if (rec) {
+    RecOp r{};
+    r.kind = 1;
+    r.mf = a;
+    rec->push_back(r);
+    return hipSuccess;
+  }
   if (!prof.on) return launch_conv_mfma(a, stream);
   const double T = op.mode == CONV_T2 ? 0 : (dim == 2 ? 9.0 : 27.0);
   double fl, by;

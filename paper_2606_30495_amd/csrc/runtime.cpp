@@ -215,6 +215,13 @@ hipError_t Ctx::conv(int mode, int epi, int tin, const void* x, const Dims& in, 
 }
 
 hipError_t Ctx::dispatch_conv(const ConvLaunch& a) {
+  if (rec) {
+    RecOp r{};
+    r.kind = 0;
+    r.conv = a;
+    rec->push_back(r);
+    return hipSuccess;
+  }
   if (!prof.on) return launch_conv(a, stream);
   double fl, by;
   conv_work(a, &fl, &by);
@@ -294,7 +301,14 @@ hipError_t Ctx::level1(Level& lv, int var, int step) {
   l.w = lv.l1w[var == L1_RESID ? 0 : step];
   l.n = lv.dims;
   hipError_t e;
-  if (!prof.on) {
+  if (rec) {
+    RecOp r{};
+    r.kind = 2;
+    r.l1 = l;
+    r.l1w_dev = lv.l1w_dev[var == L1_RESID ? 0 : step];
+    rec->push_back(r);
+    e = hipSuccess;
+  } else if (!prof.on) {
     e = launch_level1(l, stream);
   } else {
     const double P = (double)lv.dims.total, T = dim == 2 ? 9.0 : 27.0;
@@ -338,6 +352,13 @@ mcmg_status Ctx::plan_level1() {
     }
     lv.e_alt = (float*)alloc((size_t)lv.dims.total * 2 * sizeof(float));
     if (!lv.e_alt) return fail(MCMG_E_OOM, "level allocation failed");
+    lv.l1w_dev.assign(lv.l1w.size(), nullptr);
+    for (size_t i = 0; i < lv.l1w.size(); ++i) {
+      lv.l1w_dev[i] = (L1Weights*)alloc(sizeof(L1Weights));
+      if (!lv.l1w_dev[i]) return fail(MCMG_E_OOM, "weight allocation failed");
+      if (hipMemcpy(lv.l1w_dev[i], &lv.l1w[i], sizeof(L1Weights), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(MCMG_E_HIP, "weight upload failed");
+    }
   }
   return MCMG_OK;
 }

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "conv_mfma.h"
 #include "internal.h"
 #include "mcmg.h"
 
@@ -40,6 +41,7 @@ struct Level {
   std::vector<void*> m_sm;
   // fused C = 2 sweep: per smoothing step weights; e ping-pongs with e_alt
   std::vector<L1Weights> l1w;
+  std::vector<L1Weights*> l1w_dev;          // device copies (batched launches)
   float* e_alt = nullptr;
 };
 
@@ -70,6 +72,25 @@ struct Prof {
   ~Prof() {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
+};
+
+// A recorded launch of the V-cycle (record mode): the batched driver replays
+// op i of every problem as one batched launch.
+struct RecOp {
+  int kind;                   // 0 VALU direct conv, 1 matrix-core conv, 2 fused C = 2 sweep
+  ConvLaunch conv;
+  MfmaConv mf;
+  L1Launch l1;
+  const L1Weights* l1w_dev;   // device copy of the sweep's weights
+};
+
+// One right-hand side's workspace: V-cycle level state and Krylov buffers.
+struct Slot {
+  std::vector<float*> e, r, t, u, e_alt;     // per level
+  double *V = nullptr, *wv = nullptr, *rv = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr;
+  double *g = nullptr, *y = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr;
+  float *Z = nullptr, *zt = nullptr;
+  int* skip = nullptr;
 };
 
 struct HostTensor {
@@ -108,6 +129,15 @@ struct Ctx {
   std::vector<void*> allocs;
   size_t device_bytes = 0;
   Prof prof;
+  // record mode: launches are appended here instead of issued (batching)
+  std::vector<RecOp>* rec = nullptr;
+  // extra per-RHS workspaces (slot 0 is the handle's own buffers above)
+  std::vector<Slot> slots;
+
+  Slot current_slot() const;                // the buffers now bound
+  void bind_slot(const Slot& s);            // bind another workspace
+  mcmg_status ensure_slots(int n);          // slots 1..n-1 allocated
+  mcmg_status alloc_slot(Slot& s);
 
   // `launch` must capture by value: it is kept for replay.
   template <class F>

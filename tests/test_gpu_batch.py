@@ -1,0 +1,98 @@
+"""Batched FGMRES (mcmg_solve_batch): uneven grid sizes and several RHS per
+medium in one launch per operation.  Each problem's result must be the same
+alone and in the mix: the batched kernels share their bodies and per-problem
+fixed-order reductions with the single-problem path, so results are compared
+bitwise (and iteration counts exactly)."""
+import numpy as np
+import pytest
+
+import synth
+from _gpu_common import say, to_dev, to_host
+from test_gpu_solve import classical_problem, gpu_handle
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(precision):
+    sides = [(48, 6), (64, 8), (40, 4)]
+    probs, handles = [], []
+    for n, npml in sides:
+        p = classical_problem(n=n, npml=npml)
+        probs.append(p)
+        handles.append(gpu_handle(p, precision))
+    # a second right-hand side for the 64^2 medium (same handle twice)
+    rng = np.random.default_rng(9)
+    f2 = synth.point_source(64, 8, tuple(rng.uniform(0.2, 0.8, 2)), 2)
+    items = [(handles[0], probs[0]["f"]), (handles[1], probs[1]["f"]), (handles[2], probs[2]["f"]),
+             (handles[1], f2)]
+    return handles, items
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_batch_matches_single_solves(precision):
+    from paper_2606_30495_amd import solve_batch
+    say(f"[batch] {precision}")
+    handles, items = _problems(precision)
+    singles = []
+    for H, f in items:
+        u = to_dev(np.zeros_like(f))
+        info = H.solve(to_dev(f), u, tol=1e-6, maxit=500)
+        singles.append((to_host(u), info))
+    fs = [to_dev(f) for _, f in items]
+    us = [to_dev(np.zeros_like(f)) for _, f in items]
+    st, infos = solve_batch([H for H, _ in items], fs, us, tol=1e-6, maxit=500, hist_cap=600)
+    assert st == 0
+    for k, ((us_single, i1), ub, i2) in enumerate(zip(singles, us, infos)):
+        say(f"  problem {k}: single {i1['iters']} it, batch {i2['iters']} it, relres {i2['relres_true']:.3e}")
+        assert i2["converged"] and i2["relres_true"] <= 1e-6
+        assert i2["iters"] == i1["iters"]
+        assert np.array_equal(to_host(ub), us_single)
+        assert np.array_equal(np.array(i2["hist"]), np.array(i1["hist"]))
+
+
+def test_batch_alone_equals_in_mix():
+    """The same problem alone in a batch of one and inside a larger batch."""
+    from paper_2606_30495_amd import solve_batch
+    say("[batch-mix]")
+    handles, items = _problems("bf16")
+    H, f = items[1]
+    u_alone = to_dev(np.zeros_like(f))
+    solve_batch([H], [to_dev(f)], [u_alone], tol=1e-6, maxit=500)
+    fs = [to_dev(x) for _, x in items]
+    us = [to_dev(np.zeros_like(x)) for _, x in items]
+    solve_batch([h for h, _ in items], fs, us, tol=1e-6, maxit=500)
+    assert np.array_equal(to_host(us[1]), to_host(u_alone))
+
+
+def test_batch_random_weights_partial_cycles():
+    """Random-init weights (no convergence): maxit cuts every problem in the
+    middle of a cycle; the partial iterates still match the single solves."""
+    from paper_2606_30495_amd import Handle, solve_batch
+    say("[batch-random]")
+    ch, nu = (2, 8, 16), (2, 2, 2)
+    blob = synth.pack_blob(2, ch, nu, nu, synth.make_weights(2, ch, nu, nu, 0))
+    hs, fs = [], []
+    for n in (64, 37):
+        c = synth.medium_bump(n, 2)
+        h = 1.0 / n
+        hs.append(Handle(c, synth.omega_for_ppw(c, 10.0, h), h, 8, blob, restart=30))
+        fs.append(synth.point_source(n, 8, (0.5, 0.25), 2))
+    singles = []
+    for H, f in zip(hs, fs):
+        u = to_dev(np.zeros_like(f))
+        singles.append((H.solve(to_dev(f), u, tol=1e-6, maxit=45), u))
+    us = [to_dev(np.zeros_like(f)) for f in fs]
+    st, infos = solve_batch(hs, [to_dev(f) for f in fs], us, tol=1e-6, maxit=45)
+    assert st == 1
+    for (i1, u1), u2, i2 in zip(singles, us, infos):
+        assert i2["iters"] == i1["iters"] == 45 and not i2["converged"]
+        assert np.array_equal(to_host(u2), to_host(u1))
+
+
+def test_batch_rejects_mixed_precision():
+    from paper_2606_30495_amd import McmgError, solve_batch
+    p = classical_problem(n=32, npml=4)
+    h1, h2 = gpu_handle(p, "fp32"), gpu_handle(p, "bf16")
+    f = to_dev(p["f"])
+    with pytest.raises(McmgError):
+        solve_batch([h1, h2], [f, f.clone()], [f.clone() * 0, f.clone() * 0])
