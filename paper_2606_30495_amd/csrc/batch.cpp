@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <vector>
@@ -183,12 +184,20 @@ extern "C" mcmg_status mcmg_solve_batch(mcmg_handle* hs, const double* const* f,
       if (a.nu1 == 0) return fail(MCMG_E_ARG, "batched solve needs nu1 > 0 on every level");
     }
   }
-  hipStream_t s = c0->stream;
+  // The batch runs on a stream of its own (graph capture is not possible on
+  // the legacy default stream); every handle's stream is drained first, and
+  // the call returns only when the batch is done.
+  const char* genv = getenv("MCMG_GRAPHS");
+  const bool use_graphs = !(genv && genv[0] == '0');
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+    return fail(MCMG_E_HIP, "stream create failed");
+  struct StreamFree { hipStream_t s; ~StreamFree() { (void)hipStreamSynchronize(s); (void)hipStreamDestroy(s); } } sfree{s};
   // ---- workspace slots: a handle that appears k times gets k slots
   std::map<Ctx*, int> count;
   for (int i = 0; i < nb; ++i) count[(Ctx*)hs[i]]++;
   for (auto& kv : count) {
-    if (kv.first->stream != s) (void)hipStreamSynchronize(kv.first->stream);
+    if (hipStreamSynchronize(kv.first->stream) != hipSuccess) return fail(MCMG_E_HIP, "stream sync");
     mcmg_status st = kv.first->ensure_slots(kv.second);
     if (st != MCMG_OK) return st;
   }
@@ -359,6 +368,35 @@ extern "C" mcmg_status mcmg_solve_batch(mcmg_handle* hs, const double* const* f,
     }
     return hipSuccess;
   };
+  // One FGMRES iteration at Krylov position j for every live problem, ending
+  // with the gather copy to the host (no synchronisation inside, so the same
+  // sequence can be captured into a graph and replayed).
+  auto iteration = [&](int j) -> hipError_t {
+    hipError_t ee = vcycle_batched(j);
+    if (ee != hipSuccess) return ee;
+    {
+      BatchLaunch b{dt.at(hmv_off[j]), (const int*)dt.at(pre_red_off), nb, pre_red[nb], d_frozen};
+      if ((ee = launch_helm_batched(dim, T_F32, b, s)) != hipSuccess) return ee;
+    }
+    const int nv = j + 1;
+    for (int pass = 0; pass < 2; ++pass) {
+      if ((ee = kb_launch(KB_MULTIDOT, kb, nv, j, pass, m, s)) != hipSuccess) return ee;
+      if ((ee = kb_launch(KB_REDUCE_DOTS, kb, nv, j, pass, m, s)) != hipSuccess) return ee;
+      if ((ee = kb_launch(KB_UPDATE, kb, nv, j, pass, m, s)) != hipSuccess) return ee;
+      if ((ee = kb_launch(KB_REDUCE_NORM, kb, nv, j, pass, m, s)) != hipSuccess) return ee;
+    }
+    if ((ee = kb_launch(KB_GIVENS, kb, nv, j, 0, m, s)) != hipSuccess) return ee;
+    if (j + 1 < m && (ee = kb_launch(KB_SCALE_W, kb, nv, j, 0, m, s)) != hipSuccess) return ee;
+    return hipMemcpyAsync(hgather, d_gather, 4 * nb * sizeof(double), hipMemcpyDeviceToHost, s);
+  };
+  // Iterations replay one captured graph per Krylov position (MCMG_GRAPHS=0:
+  // plain launches); graph nodes hold only device table pointers, so they
+  // stay valid across cycles while the frozen flags and k change.
+  std::vector<hipGraphExec_t> gexec(m, nullptr);
+  struct GraphFree {
+    std::vector<hipGraphExec_t>* g;
+    ~GraphFree() { for (auto x : *g) if (x) (void)hipGraphExecDestroy(x); }
+  } gfree{&gexec};
   auto residual_batched = [&]() -> hipError_t {
     BatchLaunch b{dt.at(hres_off), (const int*)dt.at(pre_red_off), nb, pre_red[nb], d_frozen};
     hipError_t ee = launch_helm_batched(dim, T_F64, b, s);
@@ -416,21 +454,24 @@ extern "C" mcmg_status mcmg_solve_batch(mcmg_handle* hs, const double* const* f,
     BCK(kb_launch(KB_SCALE_R, kb, 0, 0, 0, m, s));
     BCK(kb_launch(KB_CYCLE_INIT, kb, 0, 0, 0, m, s));
     for (int j = 0; j < m; ++j) {
-      BCK(vcycle_batched(j));
-      {
-        BatchLaunch b{dt.at(hmv_off[j]), (const int*)dt.at(pre_red_off), nb, pre_red[nb], d_frozen};
-        BCK(launch_helm_batched(dim, T_F32, b, s));
+      if (use_graphs) {
+        if (!gexec[j]) {
+          hipGraph_t g = nullptr;
+          BCK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+          hipError_t ce = iteration(j);
+          hipError_t ee = hipStreamEndCapture(s, &g);
+          if (ce != hipSuccess) { if (g) (void)hipGraphDestroy(g); BCK(ce); }
+          BCK(ee);
+          ee = hipGraphInstantiate(&gexec[j], g, nullptr, nullptr, 0);
+          (void)hipGraphDestroy(g);
+          BCK(ee);
+        }
+        BCK(hipGraphLaunch(gexec[j], s));
+        BCK(hipStreamSynchronize(s));
+      } else {
+        BCK(iteration(j));
+        BCK(hipStreamSynchronize(s));
       }
-      const int nv = j + 1;
-      for (int pass = 0; pass < 2; ++pass) {
-        BCK(kb_launch(KB_MULTIDOT, kb, nv, j, pass, m, s));
-        BCK(kb_launch(KB_REDUCE_DOTS, kb, nv, j, pass, m, s));
-        BCK(kb_launch(KB_UPDATE, kb, nv, j, pass, m, s));
-        BCK(kb_launch(KB_REDUCE_NORM, kb, nv, j, pass, m, s));
-      }
-      BCK(kb_launch(KB_GIVENS, kb, nv, j, 0, m, s));
-      if (j + 1 < m) BCK(kb_launch(KB_SCALE_W, kb, nv, j, 0, m, s));
-      BCK(pull_gather());
       bool live = false;
       for (int i = 0; i < nb; ++i) {
         Prob& p = P[i];

@@ -96,3 +96,34 @@ def test_batch_rejects_mixed_precision():
     f = to_dev(p["f"])
     with pytest.raises(McmgError):
         solve_batch([h1, h2], [f, f.clone()], [f.clone() * 0, f.clone() * 0])
+
+
+def test_batch_graph_replay_equals_plain_launches(monkeypatch):
+    """Iterations replayed from captured graphs give the same bits as plain
+    launches; the batch is run twice with unrelated eager device work between
+    the calls, so later replays are checked as well as the first."""
+    import torch
+    from paper_2606_30495_amd import solve_batch
+    say("[batch-graphs]")
+    handles, items = _problems("bf16")
+    hl = [H for H, _ in items]
+
+    def run():
+        fs = [to_dev(x) for _, x in items]
+        us = [to_dev(np.zeros_like(x)) for _, x in items]
+        st, infos = solve_batch(hl, fs, us, tol=1e-6, maxit=500)
+        assert st == 0
+        return [to_host(u) for u in us], [i["iters"] for i in infos]
+
+    monkeypatch.setenv("MCMG_GRAPHS", "0")
+    u_plain, it_plain = run()
+    monkeypatch.setenv("MCMG_GRAPHS", "1")
+    for rep in range(2):
+        x = torch.randn(1 << 20, device="cuda")
+        torch.cuda.synchronize()
+        assert torch.isfinite((x * 2.0).sum()).item()
+        u_g, it_g = run()
+        say(f"  replay {rep}: iters {it_g} (plain {it_plain})")
+        assert it_g == it_plain
+        for a, b in zip(u_g, u_plain):
+            assert np.array_equal(a, b)
