@@ -123,8 +123,14 @@ mcmg_status mcmg_stationary(mcmg_handle h, const double* f, double* u,
  * together, one launch per operation for the whole batch).  hs[i] is the
  * handle of problem i (the same handle may appear several times); f[i],
  * u[i] are device arrays on that handle's extended grid.  All handles must
- * share dim, level count, channels and precision.  Work runs on hs[0]'s
- * stream.  infos: nb entries or NULL.  Blocks until all are done. */
+ * share dim, level count, channels, smoothing counts, precision and restart
+ * length (MCMG_E_ARG otherwise).  Every problem restarts on its own schedule
+ * and gets exactly the iterates mcmg_solve gives it alone.  The handles'
+ * streams are drained first; the batch runs on a stream of its own and the
+ * call blocks until all problems are done.  A handle that appears k times
+ * holds k workspaces afterwards (kept for later batches, freed with the
+ * handle).  infos: nb entries or NULL.  Returns the first negative status
+ * of any problem, else MCMG_NOT_CONVERGED if any stopped at maxit. */
 mcmg_status mcmg_solve_batch(mcmg_handle* hs, const double* const* f,
                              double* const* u, int nb, double tol, int maxit,
                              mcmg_info* infos);

@@ -288,10 +288,11 @@ __global__ __launch_bounds__(256) void mconv_kernel(MArgs A) {
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
 __global__ __launch_bounds__(256) void mconv_kernel_batched(const MArgs* __restrict__ tab,
                                                             const int* __restrict__ pre, int np,
-                                                            const int* __restrict__ frozen) {
+                                                            const int* __restrict__ frozen,
+    const int* __restrict__ row) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
-  const MArgs A = tab[p];
+  const MArgs A = tab[batch_entry(row, np, p)];
   mconv_body<D, BF, MODE, EPI, MT, NTW>(A, blockIdx.x - pre[p]);
 }
 
@@ -301,7 +302,7 @@ hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
   const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.cinp, a.epi, a.kchunk);
   if (b) {
     hipLaunchKernelGGL((mconv_kernel_batched<D, BF, MODE, EPI, MT, NTW>), dim3(b->total, nslices),
-                       dim3(256), lds, s, (const MArgs*)b->tab, b->pre, b->np, b->frozen);
+                       dim3(256), lds, s, (const MArgs*)b->tab, b->pre, b->np, b->frozen, b->row);
   } else {
     int nblk;
     const MArgs A = mfma_args(a, &nblk);

@@ -113,10 +113,11 @@ __global__ __launch_bounds__(256) void conv_direct(DArgs A) {
 template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
 __global__ __launch_bounds__(256) void conv_direct_batched(const DArgs* __restrict__ tab,
                                                            const int* __restrict__ pre, int np,
-                                                           const int* __restrict__ frozen) {
+                                                           const int* __restrict__ frozen,
+    const int* __restrict__ row) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
-  const DArgs A = tab[p];
+  const DArgs A = tab[batch_entry(row, np, p)];
   conv_body<D, CT, MODE, EPI, TIN, TOUT>(A, blockIdx.x - pre[p]);
 }
 
@@ -126,7 +127,7 @@ hipError_t run(const ConvLaunch& a, const BatchLaunch* b, hipStream_t s) {
   if (b) {
     hipLaunchKernelGGL((conv_direct_batched<D, CT, MODE, EPI, TIN, TOUT>),
                        dim3((unsigned)b->total, (unsigned)nchunk), dim3(256), 0, s,
-                       (const DArgs*)b->tab, b->pre, b->np, b->frozen);
+                       (const DArgs*)b->tab, b->pre, b->np, b->frozen, b->row);
   } else {
     int nblk;
     const DArgs A = conv_args(a, &nblk);

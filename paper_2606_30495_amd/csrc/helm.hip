@@ -108,10 +108,11 @@ __global__ __launch_bounds__(HB) void helm_kernel(HArgs A) {
 template <int D, typename TIN>
 __global__ __launch_bounds__(HB) void helm_kernel_batched(const HArgs* __restrict__ tab,
                                                           const int* __restrict__ pre, int np,
-                                                          const int* __restrict__ frozen) {
+                                                          const int* __restrict__ frozen,
+    const int* __restrict__ row) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
-  const HArgs A = tab[p];
+  const HArgs A = tab[batch_entry(row, np, p)];
   helm_body<D, TIN>(A, blockIdx.x - pre[p]);
 }
 
@@ -121,10 +122,10 @@ hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLa
   // the fastest, so 2D data is addressed as n0 x n1 x 1.
   if (b) {
     const HArgs* t = (const HArgs*)b->tab;
-    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<2, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
-    else if (dim == 2) hipLaunchKernelGGL((helm_kernel_batched<2, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
-    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<3, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
-    else hipLaunchKernelGGL((helm_kernel_batched<3, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen);
+    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<2, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
+    else if (dim == 2) hipLaunchKernelGGL((helm_kernel_batched<2, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
+    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<3, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
+    else hipLaunchKernelGGL((helm_kernel_batched<3, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
   } else {
     if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel<2, double>), dim3(nb), dim3(HB), 0, s, *A);
     else if (dim == 2) hipLaunchKernelGGL((helm_kernel<2, float>), dim3(nb), dim3(HB), 0, s, *A);

@@ -148,12 +148,11 @@ struct KArgs {
   int* skip;
   long long N;        // extended-grid nodes
   int ldh;            // m + 1
-  int k;              // iterations of the current cycle (solution update)
   int always_two;     // force the second Gram-Schmidt pass
 };
 enum {
   KB_MULTIDOT, KB_REDUCE_DOTS, KB_UPDATE, KB_REDUCE_NORM, KB_GIVENS, KB_SCALE_R, KB_SCALE_W,
-  KB_CYCLE_INIT, KB_BACKSOLVE, KB_ZUPDATE, KB_REDUCE_SUM
+  KB_CYCLE_INIT, KB_BACKSOLVE, KB_ZUPDATE, KB_REDUCE_SUM, KB_FNORM_PARTIAL, KB_FNORM_REDUCE
 };
 struct KBatch {
   const KArgs* tab;       // device table, np entries
@@ -163,9 +162,11 @@ struct KBatch {
   const int* pre_elem;    // block prefix for elem_blocks(N) grids
   int total_elem;
   const int* frozen;      // device flags (may be null)
-  double* gather;         // device, 4 doubles per problem: (rho, h_{j+1,j}, |col|, |r|)
+  const int* jpos;        // device, Krylov position j per problem
+  const int* kk;          // device, length of the cycle being closed per problem
+  double* gather;         // device, 4 doubles per problem: (rho or |f|^2, h_{j+1,j}, |col|, |r|)
 };
-hipError_t kb_launch(int op, const KBatch& b, int nvec, int j, int pass, int m, hipStream_t s);
+hipError_t kb_launch(int op, const KBatch& b, int pass, int m, hipStream_t s);
 
 }  // namespace mcmg
 
@@ -194,14 +195,21 @@ namespace mcmg {
 // A batched kernel runs several independent problems in one launch: tab is a
 // device array of per-problem argument structs, pre (np + 1 ints, device)
 // the prefix of per-problem block counts, total = pre[np]; frozen (np ints,
-// device, may be null) marks problems whose blocks return at once.
+// device, may be null) marks problems whose blocks return at once.  A table
+// may hold several rows of np entries (one per Krylov position); row (np
+// ints, device, may be null = row 0) selects each problem's row.
 struct BatchLaunch {
   const void* tab;
   const int* pre;
   int np;
   int total;
   const int* frozen;
+  const int* row = nullptr;
 };
+
+__host__ __device__ __forceinline__ int batch_entry(const int* row, int np, int p) {
+  return (row ? row[p] * np : 0) + p;
+}
 
 // Problem of launch block b: the last p with pre[p] <= b (pre is ascending;
 // every lane takes the same path, so the loads are wave-uniform).

@@ -335,39 +335,46 @@ __global__ void copy_kernel(const double* __restrict__ a, double* __restrict__ b
 }
 
 // ---- batched kernels ---------------------------------------------------------
-// pre: per-problem block prefix; frozen: per-problem skip flag (may be null).
+// pre: per-problem block prefix; frozen: per-problem skip flag (may be null);
+// jpos: per-problem Krylov position j (column of H, nvec = j + 1 basis
+// vectors); kk: per-problem length of the cycle being closed.
 
 __device__ __forceinline__ bool is_frozen(const int* frozen, int p) { return frozen && frozen[p]; }
 
 __global__ __launch_bounds__(RB) void kb_multidot(const KArgs* __restrict__ tab,
                                                   const int* __restrict__ pre, int np,
-                                                  const int* __restrict__ frozen, int nvec, int pass) {
+                                                  const int* __restrict__ frozen,
+                                                  const int* __restrict__ jpos, int pass) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
   if (pass == 1 && A.skip[0]) return;
-  multidot_body(A.V, A.N, nvec, A.w, A.N, A.partial, red_blocks(A.N), blockIdx.x - pre[p]);
+  multidot_body(A.V, A.N, jpos[p] + 1, A.w, A.N, A.partial, red_blocks(A.N), blockIdx.x - pre[p]);
 }
 
+// grid (m + 1, np): block x reduces output x of problem y (x == nvec: |w|^2)
 __global__ __launch_bounds__(RB) void kb_reduce_dots(const KArgs* __restrict__ tab,
-                                                     const int* __restrict__ frozen, int nvec, int j,
-                                                     int pass) {
+                                                     const int* __restrict__ frozen,
+                                                     const int* __restrict__ jpos, int pass) {
   const int p = blockIdx.y;
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
+  const int j = jpos[p];
+  if ((int)blockIdx.x > j + 1) return;
   if (pass == 1 && A.skip[0]) return;
-  reduce_dots_body(A.partial, red_blocks(A.N), nvec, A.coef, A.H + 2LL * j * A.ldh,
+  reduce_dots_body(A.partial, red_blocks(A.N), j + 1, A.coef, A.H + 2LL * j * A.ldh,
                    A.scal + (pass == 0 ? 8 : 10), blockIdx.x);
 }
 
 __global__ __launch_bounds__(RB) void kb_update(const KArgs* __restrict__ tab,
                                                 const int* __restrict__ pre, int np,
-                                                const int* __restrict__ frozen, int nvec, int pass) {
+                                                const int* __restrict__ frozen,
+                                                const int* __restrict__ jpos, int pass) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
   if (pass == 1 && A.skip[0]) return;
-  update_body(A.V, A.N, nvec, A.coef, A.w, A.N, A.partial, blockIdx.x - pre[p]);
+  update_body(A.V, A.N, jpos[p] + 1, A.coef, A.w, A.N, A.partial, blockIdx.x - pre[p]);
 }
 
 __global__ __launch_bounds__(RB) void kb_reduce_norm(const KArgs* __restrict__ tab,
@@ -380,12 +387,12 @@ __global__ __launch_bounds__(RB) void kb_reduce_norm(const KArgs* __restrict__ t
                    pass == 0 ? A.always_two : 0);
 }
 
-__global__ void kb_givens(const KArgs* __restrict__ tab, const int* __restrict__ frozen, int j,
-                          double* __restrict__ gather) {
+__global__ void kb_givens(const KArgs* __restrict__ tab, const int* __restrict__ frozen,
+                          const int* __restrict__ jpos, double* __restrict__ gather) {
   const int p = blockIdx.x;
   if (threadIdx.x != 0 || is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  givens_body(A.H, A.ldh, j, A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
+  givens_body(A.H, A.ldh, jpos[p], A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
   gather[4 * p + 0] = A.scal[16];
   gather[4 * p + 1] = A.scal[17];
   gather[4 * p + 2] = A.scal[18];
@@ -394,14 +401,15 @@ __global__ void kb_givens(const KArgs* __restrict__ tab, const int* __restrict__
 // mode 0: V_0 = r / |r|  (|r| in scal[3]);  mode 1: V_{j+1} = w / h_{j+1,j}
 __global__ __launch_bounds__(RB) void kb_scale(const KArgs* __restrict__ tab,
                                                const int* __restrict__ pre, int np,
-                                               const int* __restrict__ frozen, int mode, int j) {
+                                               const int* __restrict__ frozen,
+                                               const int* __restrict__ jpos, int mode) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
   const long long q = (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x;
   if (q >= A.N) return;
   const double* src = mode == 0 ? A.r : A.w;
-  double* dst = A.V + (mode == 0 ? 0LL : 2LL * (j + 1) * A.N);
+  double* dst = A.V + (mode == 0 ? 0LL : 2LL * (jpos[p] + 1) * A.N);
   const double inv = 1.0 / (mode == 0 ? A.scal[3] : A.scal[9]);
   dst[2 * q] = src[2 * q] * inv;
   dst[2 * q + 1] = src[2 * q + 1] * inv;
@@ -418,19 +426,22 @@ __global__ __launch_bounds__(RB) void kb_cycle_init(const KArgs* __restrict__ ta
   for (int i = threadIdx.x; i < 2 * (m + 1); i += RB) A.g[i] = (i == 0) ? A.scal[3] : 0.0;
 }
 
-__global__ void kb_backsolve(const KArgs* __restrict__ tab) {
+__global__ void kb_backsolve(const KArgs* __restrict__ tab, const int* __restrict__ frozen,
+                             const int* __restrict__ kk) {
   const int p = blockIdx.x;
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  if (A.k > 0) backsolve_body(A.H, A.ldh, A.k, A.g, A.y);
+  if (kk[p] > 0) backsolve_body(A.H, A.ldh, kk[p], A.g, A.y);
 }
 
 __global__ __launch_bounds__(RB) void kb_zupdate(const KArgs* __restrict__ tab,
-                                                 const int* __restrict__ pre, int np) {
+                                                 const int* __restrict__ pre, int np,
+                                                 const int* __restrict__ frozen,
+                                                 const int* __restrict__ kk) {
   const int p = batch_find(pre, np, blockIdx.x);
+  if (is_frozen(frozen, p) || kk[p] <= 0) return;
   const KArgs& A = tab[p];
-  if (A.k <= 0) return;
-  zupdate_body(A.Z, A.N, A.k, A.y, A.u, A.N, (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x);
+  zupdate_body(A.Z, A.N, kk[p], A.y, A.u, A.N, (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x);
 }
 
 // |f - A u| after the batched residual kernel: scal[2] = |r|^2, scal[3] = |r|
@@ -442,6 +453,27 @@ __global__ __launch_bounds__(RB) void kb_reduce_sum(const KArgs* __restrict__ ta
   const KArgs& A = tab[p];
   reduce_sum_body(A.partial, red_blocks(A.N), A.scal + 2);
   if (threadIdx.x == 0) gather[4 * p + 3] = A.scal[3];
+}
+
+// |f|^2: per-block partials of f (the multi-dot with no basis vectors), then
+// the same fixed-order reduction the single-problem solver uses.
+__global__ __launch_bounds__(RB) void kb_fnorm_partial(const KArgs* __restrict__ tab,
+                                                       const int* __restrict__ pre, int np,
+                                                       const int* __restrict__ frozen) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  multidot_body(nullptr, A.N, 0, A.f, A.N, A.partial, red_blocks(A.N), blockIdx.x - pre[p]);
+}
+
+__global__ __launch_bounds__(RB) void kb_fnorm_reduce(const KArgs* __restrict__ tab,
+                                                      const int* __restrict__ frozen,
+                                                      double* __restrict__ gather) {
+  const int p = blockIdx.x;
+  if (is_frozen(frozen, p)) return;
+  const KArgs& A = tab[p];
+  reduce_dots_body(A.partial, red_blocks(A.N), 0, A.coef, A.coef, A.scal + 0, 0);
+  if (threadIdx.x == 0) gather[4 * p + 0] = A.scal[0];
 }
 
 inline unsigned nblk(long long n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -531,46 +563,54 @@ hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t 
 
 // ---- batched launchers ------------------------------------------------------
 
-hipError_t kb_launch(int op, const KBatch& b, int nvec, int j, int pass, int m, hipStream_t s) {
+hipError_t kb_launch(int op, const KBatch& b, int pass, int m, hipStream_t s) {
   if (b.np == 0) return hipSuccess;
   switch (op) {
     case KB_MULTIDOT:
       hipLaunchKernelGGL(kb_multidot, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red, b.np,
-                         b.frozen, nvec, pass);
+                         b.frozen, b.jpos, pass);
       break;
     case KB_REDUCE_DOTS:
-      hipLaunchKernelGGL(kb_reduce_dots, dim3(nvec + 1, b.np), dim3(RB), 0, s, b.tab, b.frozen,
-                         nvec, j, pass);
+      hipLaunchKernelGGL(kb_reduce_dots, dim3(m + 1, b.np), dim3(RB), 0, s, b.tab, b.frozen,
+                         b.jpos, pass);
       break;
     case KB_UPDATE:
       hipLaunchKernelGGL(kb_update, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red, b.np,
-                         b.frozen, nvec, pass);
+                         b.frozen, b.jpos, pass);
       break;
     case KB_REDUCE_NORM:
       hipLaunchKernelGGL(kb_reduce_norm, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, pass);
       break;
     case KB_GIVENS:
-      hipLaunchKernelGGL(kb_givens, dim3(b.np), dim3(64), 0, s, b.tab, b.frozen, j, b.gather);
+      hipLaunchKernelGGL(kb_givens, dim3(b.np), dim3(64), 0, s, b.tab, b.frozen, b.jpos, b.gather);
       break;
     case KB_SCALE_R:
       hipLaunchKernelGGL(kb_scale, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,
-                         b.frozen, 0, j);
+                         b.frozen, b.jpos, 0);
       break;
     case KB_SCALE_W:
       hipLaunchKernelGGL(kb_scale, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,
-                         b.frozen, 1, j);
+                         b.frozen, b.jpos, 1);
       break;
     case KB_CYCLE_INIT:
       hipLaunchKernelGGL(kb_cycle_init, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, m);
       break;
     case KB_BACKSOLVE:
-      hipLaunchKernelGGL(kb_backsolve, dim3(b.np), dim3(64), 0, s, b.tab);
+      hipLaunchKernelGGL(kb_backsolve, dim3(b.np), dim3(64), 0, s, b.tab, b.frozen, b.kk);
       break;
     case KB_ZUPDATE:
-      hipLaunchKernelGGL(kb_zupdate, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np);
+      hipLaunchKernelGGL(kb_zupdate, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,
+                         b.frozen, b.kk);
       break;
     case KB_REDUCE_SUM:
       hipLaunchKernelGGL(kb_reduce_sum, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, b.gather);
+      break;
+    case KB_FNORM_PARTIAL:
+      hipLaunchKernelGGL(kb_fnorm_partial, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red,
+                         b.np, b.frozen);
+      break;
+    case KB_FNORM_REDUCE:
+      hipLaunchKernelGGL(kb_fnorm_reduce, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, b.gather);
       break;
     default:
       return hipErrorInvalidValue;

@@ -234,10 +234,11 @@ __global__ __launch_bounds__(NTH) void l1_kernel(L1Args A, L1Weights w) {
 template <int D, int VAR>
 __global__ __launch_bounds__(NTH) void l1_kernel_batched(const L1Args* __restrict__ tab,
                                                          const int* __restrict__ pre, int np,
-                                                         const int* __restrict__ frozen) {
+                                                         const int* __restrict__ frozen,
+    const int* __restrict__ row) {
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
-  const L1Args A = tab[p];
+  const L1Args A = tab[batch_entry(row, np, p)];
   l1_body<D, VAR>(A, *A.wp, blockIdx.x - pre[p]);
 }
 
@@ -245,7 +246,7 @@ template <int D, int VAR>
 hipError_t run(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
   if (b) {
     hipLaunchKernelGGL((l1_kernel_batched<D, VAR>), dim3(b->total), dim3(NTH), 0, s,
-                       (const L1Args*)b->tab, b->pre, b->np, b->frozen);
+                       (const L1Args*)b->tab, b->pre, b->np, b->frozen, b->row);
   } else {
     int nblk;
     const L1Args A = l1_args(l, nullptr, &nblk);

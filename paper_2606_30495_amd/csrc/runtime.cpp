@@ -53,6 +53,7 @@ void* Ctx::alloc(size_t bytes) {
 
 Ctx::~Ctx() {
   if (stream) (void)hipStreamSynchronize(stream);
+  for (Slot& sl : slots) if (sl.chunk) (void)hipFree(sl.chunk);
   for (void* p : allocs) (void)hipFree(p);
   if (host_scal) (void)hipHostFree(host_scal);
 }
@@ -569,7 +570,13 @@ mcmg_status mcmg_setup(const double* c, mcmg_grid grid, double omega, double h, 
 
 void mcmg_destroy(mcmg_handle h) { delete (Ctx*)h; }
 
-size_t mcmg_device_bytes(mcmg_handle h) { return h ? ((Ctx*)h)->device_bytes : 0; }
+size_t mcmg_device_bytes(mcmg_handle h) {
+  if (!h) return 0;
+  const Ctx* c = (const Ctx*)h;
+  size_t n = c->device_bytes;
+  for (const Slot& s : c->slots) n += s.bytes;
+  return n;
+}
 
 mcmg_status mcmg_grid_shape(mcmg_handle h, int* dim, int n_ext[3], int* npml) {
   if (!h) return fail(MCMG_E_ARG, "null handle");

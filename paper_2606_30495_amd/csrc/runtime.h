@@ -91,6 +91,8 @@ struct Slot {
   double *g = nullptr, *y = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr;
   float *Z = nullptr, *zt = nullptr;
   int* skip = nullptr;
+  void* chunk = nullptr;                     // owning allocation (null: the handle's own)
+  size_t bytes = 0;
 };
 
 struct HostTensor {
@@ -137,7 +139,10 @@ struct Ctx {
   Slot current_slot() const;                // the buffers now bound
   void bind_slot(const Slot& s);            // bind another workspace
   mcmg_status ensure_slots(int n);          // slots 1..n-1 allocated
-  mcmg_status alloc_slot(Slot& s);
+  mcmg_status alloc_slot(Slot& s);          // one device chunk
+  void free_slot(Slot& s);
+  size_t slot_bytes() const;                // device bytes of one extra slot
+  size_t slot_layout(Slot* s, unsigned char* base) const;
 
   // `launch` must capture by value: it is kept for replay.
   template <class F>
