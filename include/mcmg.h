@@ -170,6 +170,90 @@ mcmg_status mcmg_debug_set_features(mcmg_handle h, int level, const float* a,
 mcmg_status mcmg_debug_get_features(mcmg_handle h, int level, float* a, float* s);
 mcmg_status mcmg_debug_level_shape(mcmg_handle h, int level, int n[3], int* channels);
 
+/* ---- Serving loop -----------------------------------------------------------
+ * A server owns media (handles after their setup phase: features, operator
+ * tables, weights stay resident) and solves requests of 1..n right-hand
+ * sides on them with continuous batching: a worker thread advances every
+ * right-hand side in flight by one FGMRES step per tick (the batch engine of
+ * mcmg_solve_batch: one launch per operation for all of them, captured in a
+ * HIP graph while the set is unchanged), admits queued requests between
+ * ticks as workspace slots and HBM budget free up, and retires right-hand
+ * sides as they converge.  Media of different families (2D / 3D, level
+ * structures, precision) advance on separate streams, so their work
+ * overlaps on the device.  Every result is bitwise the one mcmg_solve gives
+ * the same handle, right-hand side and initial guess alone.
+ *
+ * Memory: the budget covers every medium's handle (mcmg_device_bytes at
+ * admission, which includes one workspace) plus every extra workspace slot
+ * (Krylov basis V in FP64, Z in FP32, V-cycle level state).  Requests are
+ * admitted in arrival order; a request waits until all of its right-hand
+ * sides fit (idle slots of other media are released to make room).  */
+typedef struct mcmg_server_s* mcmg_server;
+
+typedef struct {
+  size_t hbm_budget;   /* bytes the server may hold on the device (> 0)     */
+  int max_inflight;    /* cap on right-hand sides in flight; 0 = no cap     */
+  int graphs;          /* 1: replay captured ticks (default); 0: launches   */
+} mcmg_server_opts;
+
+typedef struct {
+  uint64_t req_id;
+  int status;          /* worst mcmg_status of its right-hand sides         */
+  int nrhs;
+  int iters_total;     /* preconditioner applications over its rhs          */
+  int iters_max;
+  double relres_max;   /* largest FP64 true relative residual at exit       */
+  double queue_s;      /* submit -> admitted (seconds)                      */
+  double latency_s;    /* submit -> every solution written (seconds)        */
+} mcmg_completion;
+
+typedef struct {
+  size_t bytes_in_use;     /* media + slots now allocated                   */
+  size_t bytes_peak;
+  int media, slots, inflight, queued, completed;
+  int inflight_peak;       /* most right-hand sides in flight at once       */
+  long long ticks;         /* engine ticks issued                           */
+  long long rebuilds;      /* composition changes (tables rebuilt)          */
+} mcmg_server_stats;
+
+/* E_ARG for a null or zero budget.  The worker thread starts at once. */
+mcmg_status mcmg_server_create(const mcmg_server_opts* opts, mcmg_server* out);
+
+/* Adds a medium: runs mcmg_setup with these arguments (opt->stream is
+ * ignored).  E_BUDGET when its handle does not fit next to the media
+ * already held; *medium_id is the medium's index (0, 1, ...). */
+mcmg_status mcmg_server_add_medium(mcmg_server s, const double* c, mcmg_grid grid,
+                                   double omega, double h, mcmg_pml pml, mcmg_weights w,
+                                   const mcmg_opts* opt, int* medium_id);
+
+/* Adds an existing handle as a medium; the server takes ownership (the
+ * caller must not use or destroy it afterwards, also on error). */
+mcmg_status mcmg_server_add_handle(mcmg_server s, mcmg_handle h, int* medium_id);
+
+/* Queues a request of nrhs right-hand sides on medium_id.  f[i], u[i]:
+ * device complex128 on the medium's extended grid; u[i] is the initial
+ * guess in and the solution out.  The caller keeps all of them alive and
+ * untouched until the request's completion is polled, and f[i], u[i] must
+ * be fully written when this is called (the server's streams do not wait
+ * for the caller's).  Returns at once.  E_BUDGET if the request could
+ * never fit the budget (or max_inflight); E_ARG for bad arguments. */
+mcmg_status mcmg_server_submit(mcmg_server s, int medium_id, const double* const* f,
+                               double* const* u, int nrhs, double tol, int maxit,
+                               uint64_t* req_id);
+
+/* Moves up to max finished requests into out (oldest first), waiting up to
+ * wait_ms milliseconds for the first one (0: no wait).  Returns the
+ * worker's error (negative) if it stopped on one; the requests it held are
+ * then completed with that status. */
+mcmg_status mcmg_server_poll(mcmg_server s, mcmg_completion* out, int max, int* n,
+                             int wait_ms);
+
+mcmg_status mcmg_server_get_stats(mcmg_server s, mcmg_server_stats* out);
+
+/* Stops the worker (requests still queued or in flight are abandoned; their
+ * buffers are no longer touched once this returns) and frees every medium. */
+void mcmg_server_destroy(mcmg_server s);
+
 #ifdef __cplusplus
 }
 #endif

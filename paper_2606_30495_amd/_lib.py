@@ -50,6 +50,25 @@ class Info(ctypes.Structure):
                 ("hist_cap", ctypes.c_int), ("hist_len", ctypes.c_int)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_inflight", ctypes.c_int),
+                ("graphs", ctypes.c_int)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int), ("nrhs", ctypes.c_int),
+                ("iters_total", ctypes.c_int), ("iters_max", ctypes.c_int),
+                ("relres_max", ctypes.c_double), ("queue_s", ctypes.c_double),
+                ("latency_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("bytes_in_use", ctypes.c_size_t), ("bytes_peak", ctypes.c_size_t),
+                ("media", ctypes.c_int), ("slots", ctypes.c_int), ("inflight", ctypes.c_int),
+                ("queued", ctypes.c_int), ("completed", ctypes.c_int),
+                ("inflight_peak", ctypes.c_int), ("ticks", ctypes.c_longlong), ("rebuilds", ctypes.c_longlong)]
+
+
 _lib = None
 
 EXPORTS = {
@@ -83,6 +102,19 @@ EXPORTS = {
     "mcmg_debug_level_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int),
                                               ctypes.POINTER(ctypes.c_int)]),
+    "mcmg_server_create": (ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
+    "mcmg_server_add_medium": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), Grid,
+                                              ctypes.c_double, ctypes.c_double, Pml, Weights,
+                                              ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_int)]),
+    "mcmg_server_add_handle": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_int)]),
+    "mcmg_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]),
+    "mcmg_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Completion), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int), ctypes.c_int]),
+    "mcmg_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "mcmg_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 
@@ -242,3 +274,85 @@ def solve_batch(handles, fs, us, tol=1e-6, maxit=500, hist_cap=0):
                     "hist": list(hists[i][: infos[i].hist_len]),
                     "converged": infos[i].status == MCMG_OK})
     return st, out
+
+
+class Server:
+    """Serving loop (continuous batching under an HBM budget); see the
+    mcmg_server_* entry points.  Media are Handles (ownership moves to the
+    server) or set up in place; requests carry device f / u tensors that
+    must stay alive until their completion is polled."""
+
+    def __init__(self, hbm_budget, max_inflight=0, graphs=True):
+        out = ctypes.c_void_p()
+        o = ServerOpts(int(hbm_budget), int(max_inflight), 1 if graphs else 0)
+        _check(lib().mcmg_server_create(ctypes.byref(o), ctypes.byref(out)))
+        self.ptr = out
+        self._shapes = []
+        self._held = {}
+
+    def add_handle(self, handle):
+        mid = ctypes.c_int()
+        ptr, handle.ptr = handle.ptr, None        # the server owns it now
+        _check(lib().mcmg_server_add_handle(self.ptr, ptr, ctypes.byref(mid)))
+        self._shapes.append(handle.ext_shape)
+        return mid.value
+
+    def add_medium(self, c, omega, h, npml, blob, precision="bf16", restart=30, sigma_max=0.0,
+                   ortho=0):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        g = Grid(c.ndim, (ctypes.c_int * 3)(*(list(c.shape) + [1] * (3 - c.ndim))))
+        b = bytes(blob)
+        w = Weights(ctypes.cast(ctypes.c_char_p(b), ctypes.c_void_p), len(b))
+        opts = Opts(PRECISION[precision], int(restart), None, int(ortho))
+        mid = ctypes.c_int()
+        _check(lib().mcmg_server_add_medium(self.ptr, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            g, float(omega), float(h), Pml(int(npml), float(sigma_max)),
+                                            w, ctypes.byref(opts), ctypes.byref(mid)))
+        self._shapes.append(tuple(s + 2 * int(npml) for s in c.shape))
+        return mid.value
+
+    def submit(self, medium, fs, us, tol=1e-6, maxit=500):
+        import torch
+        shape = self._shapes[medium]
+        for t in list(fs) + list(us):
+            if t.dtype != torch.complex128 or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"expected contiguous complex128 {shape}")
+        n = len(fs)
+        F = (ctypes.c_void_p * n)(*[f.data_ptr() for f in fs])
+        U = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+        rid = ctypes.c_uint64()
+        _check(lib().mcmg_server_submit(self.ptr, int(medium), F, U, n, float(tol), int(maxit),
+                                        ctypes.byref(rid)))
+        self._held[rid.value] = (list(fs), list(us))
+        return rid.value
+
+    def poll(self, max_n=64, wait_ms=0):
+        buf = (Completion * max_n)()
+        n = ctypes.c_int()
+        _check(lib().mcmg_server_poll(self.ptr, buf, max_n, ctypes.byref(n), int(wait_ms)))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            self._held.pop(c.req_id, None)
+            out.append({"req_id": c.req_id, "status": c.status, "nrhs": c.nrhs,
+                        "iters_total": c.iters_total, "iters_max": c.iters_max,
+                        "relres_max": c.relres_max, "queue_s": c.queue_s,
+                        "latency_s": c.latency_s})
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(lib().mcmg_server_get_stats(self.ptr, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            lib().mcmg_server_destroy(self.ptr)
+            self.ptr = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -136,6 +136,7 @@ mcmg_status Engine::build() {
   if (hipStreamSynchronize(s_) != hipSuccess) return fail(MCMG_E_HIP, "engine sync");
   if (graph_) { (void)hipGraphExecDestroy(graph_); graph_ = nullptr; }
   ticks_same_ = 0;
+  ++rebuilds;
   const int np = (int)works_.size();
   np_ = np;
   vt_.clear();

@@ -71,6 +71,7 @@ class Engine {
   int size() const { return (int)works_.size(); }
   hipStream_t stream() const { return s_; }
   bool use_graphs = true;
+  long long rebuilds = 0;          // composition changes seen (tables rebuilt)
 
  private:
   mcmg_status build();

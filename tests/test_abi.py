@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
     # the binding covers the same names
     for n in names:
-        assert n in _lib.EXPORTS or n.startswith("mcmg_server"), n
+        assert n in _lib.EXPORTS, n
 
 
 def test_blob_layout_roundtrip():

@@ -1,0 +1,157 @@
+"""Serving loop (mcmg_server_*): continuous batching of solve requests over
+resident media under an HBM budget.  Every result must be the one the same
+handle gives the same right-hand side alone (mcmg_solve): the engine shares
+the single-problem path's kernels and fixed-order per-problem reductions, so
+u is compared bitwise and iteration counts exactly."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from _gpu_common import say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _classical(n, npml, dim=2, channels=(2, 8, 16), ppw=10.0):
+    L = len(channels)
+    nu = (2,) * L
+    c = synth.medium_bump(n, dim)
+    h = 1.0 / n
+    omega = synth.omega_for_ppw(c, ppw, h)
+    tens, feats = synth.shifted_laplacian(c, omega, h, npml, channels, nu, nu)
+    return {"n": n, "npml": npml, "dim": dim, "c": c, "h": h, "omega": omega, "feats": feats,
+            "blob": synth.pack_blob(dim, channels, nu, nu, tens)}
+
+
+def _handle(p, precision):
+    from paper_2606_30495_amd import Handle
+    H = Handle(p["c"], p["omega"], p["h"], p["npml"], p["blob"], precision=precision)
+    for l, (a, s) in enumerate(p["feats"], start=1):
+        H.set_features(l, to_dev(a), to_dev(s))
+    return H
+
+
+def _sources(p, k, seed):
+    rng = np.random.default_rng(seed)
+    return [synth.point_source(p["n"], p["npml"], tuple(rng.uniform(0.2, 0.8, p["dim"])), p["dim"])
+            for _ in range(k)]
+
+
+def _alone(p, precision, fs, maxit):
+    H = _handle(p, precision)
+    out = []
+    for f in fs:
+        u = to_dev(np.zeros_like(f))
+        info = H.solve(to_dev(f), u, tol=1e-6, maxit=maxit)
+        out.append((to_host(u), info))
+    H.close()
+    return out
+
+
+def _drain(srv, want, timeout=120.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < want:
+        for c in srv.poll(64, wait_ms=50):
+            got[c["req_id"]] = c
+        assert time.time() - t0 < timeout, f"server stalled with {len(got)}/{want} done: {srv.stats()}"
+    return got
+
+
+def test_server_results_equal_alone_with_arrivals_in_flight():
+    """Requests on three 2D media and one 3D medium (two engine families on
+    separate streams), the later ones submitted while the first are still
+    iterating; each u equals the alone solve bitwise."""
+    import torch
+    from paper_2606_30495_amd import Server
+    say("[server-mix]")
+    prec = "bf16"
+    media = [_classical(48, 6), _classical(64, 8), _classical(40, 4),
+             _classical(16, 3, dim=3, channels=(2, 4, 8), ppw=8.0)]
+    plan = [(0, 2, 1), (1, 1, 2), (3, 2, 3), (2, 3, 4), (1, 2, 5), (0, 1, 6)]
+    maxit = 300
+    srv = Server(hbm_budget=8 << 30)
+    mids = [srv.add_handle(_handle(p, prec)) for p in media]
+    reqs = []
+    early = {}
+    for q, (m, k, seed) in enumerate(plan):
+        fs = _sources(media[m], k, seed)
+        fd = [to_dev(f) for f in fs]
+        ud = [to_dev(np.zeros_like(f)) for f in fs]
+        torch.cuda.synchronize()
+        rid = srv.submit(mids[m], fd, ud, tol=1e-6, maxit=maxit)
+        reqs.append((rid, m, fs, ud))
+        if q == 2:
+            # let the first requests get going before the rest arrive
+            first = srv.poll(64, wait_ms=5)
+            assert all(c["status"] >= 0 for c in first)
+            early = {c["req_id"]: c for c in first}
+    got = _drain(srv, len(plan) - len(early))
+    got.update(early)
+    st = srv.stats()
+    say(f"  stats {st}")
+    assert st["completed"] == len(plan) and st["inflight"] == 0 and st["queued"] == 0
+    assert st["bytes_peak"] <= 8 << 30
+    for rid, m, fs, ud in reqs:
+        c = got[rid]
+        ref = _alone(media[m], prec, fs, maxit)
+        say(f"  req {rid} medium {m}: status {c['status']} iters {c['iters_total']} "
+            f"(alone {[i['iters'] for _, i in ref]}) latency {c['latency_s'] * 1e3:.1f} ms")
+        assert c["iters_total"] == sum(i["iters"] for _, i in ref)
+        assert c["iters_max"] == max(i["iters"] for _, i in ref)
+        for (u_ref, _), u in zip(ref, ud):
+            assert np.array_equal(to_host(u), u_ref)
+        if media[m]["dim"] == 2:
+            assert c["status"] == 0 and c["relres_max"] <= 1e-6
+    srv.close()
+
+
+def test_server_budget_admission_queues_and_releases():
+    """A budget that holds the medium plus one extra workspace: requests of
+    two right-hand sides run one at a time, the rest wait in the queue; the
+    peak stays inside the budget and every result still equals the alone
+    solve.  A request that can never fit is refused at submit."""
+    import torch
+    from paper_2606_30495_amd import McmgError, Server
+    say("[server-budget]")
+    prec = "fp32"
+    p = _classical(48, 6)
+    H = _handle(p, prec)
+    base = H.device_bytes()
+    # one extra workspace of this medium (same layout as the library's slot)
+    probe = Server(hbm_budget=1 << 40)
+    mid = probe.add_handle(_handle(p, prec))
+    f0 = [to_dev(x) for x in _sources(p, 2, 0)]
+    u0 = [torch.zeros_like(x) for x in f0]
+    torch.cuda.synchronize()
+    probe.submit(mid, f0, u0)
+    _drain(probe, 1)
+    slot = probe.stats()["bytes_in_use"] - base
+    probe.close()
+    assert slot > 0
+    budget = base + slot + slot // 2
+    srv = Server(hbm_budget=budget)
+    mid = srv.add_handle(H)
+    with pytest.raises(McmgError):
+        srv.submit(mid, f0 * 2, [torch.zeros_like(x) for x in f0 * 2])   # 4 rhs never fit
+    reqs = []
+    for seed in range(4):
+        fs = _sources(p, 2, 10 + seed)
+        fd = [to_dev(f) for f in fs]
+        ud = [to_dev(np.zeros_like(f)) for f in fs]
+        torch.cuda.synchronize()
+        reqs.append((srv.submit(mid, fd, ud), fs, ud))
+    st = srv.stats()
+    got = _drain(srv, len(reqs))
+    st = srv.stats()
+    say(f"  budget {budget} stats {st}")
+    assert st["bytes_peak"] <= budget and st["slots"] <= 1
+    assert st["inflight_peak"] == 2          # one two-rhs request at a time
+    for rid, fs, ud in reqs:
+        assert got[rid]["status"] == 0
+        ref = _alone(p, prec, fs, 500)
+        for (u_ref, _), u in zip(ref, ud):
+            assert np.array_equal(to_host(u), u_ref)
+    srv.close()
