@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--single", action="store_true", help="skip the other-precision leg")
     ap.add_argument("--solves", type=int, default=50,
                     help="right-hand sides of the solve-to-tolerance leg (0: skip)")
+    ap.add_argument("--batched-iters", type=int, default=30,
+                    help="iterations of the batched leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     return ap.parse_args()
@@ -150,6 +155,177 @@ def solves_leg(precision, nrhs, seed=5):
             "converged": ok, "max_relres_true": worst}
 
 
+def batched_leg(precision, iters):
+    """The batched workload (64 independent 2D problems, sides drawn from
+    {128, 256, 384, 512, 768}, high-contrast ellipses, 5 levels 2/8/16/32/64,
+    random-init weights): `iters` FGMRES iterations of every problem in one
+    engine (one launch per operation for all 64, captured tick replayed),
+    against the same iterations one problem at a time through mcmg_solve.
+    Random-init weights do not converge, so every problem runs exactly
+    `iters` iterations in both forms and the results are bitwise equal."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_30495_amd import Handle, solve_batch
+    cfg = synth.CONFIGS["ellipses64"]
+    probs = synth.make_batch(cfg)
+    tens = synth.make_weights(2, cfg.channels, cfg.nu1, cfg.nu2, cfg.weight_seed)
+    blob = synth.pack_blob(2, cfg.channels, cfg.nu1, cfg.nu2, tens)
+    t0 = time.perf_counter()
+    hs = [Handle(p["c"], p["omega"], p["h"], cfg.npml, blob, precision=precision,
+                 restart=cfg.restart) for p in probs]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    fs = [torch.from_numpy(p["f"]).cuda() for p in probs]
+    us = [torch.zeros_like(f) for f in fs]
+    solve_batch(hs, fs, us, tol=cfg.tol, maxit=2)           # warm-up (workspaces, tables)
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, infos = solve_batch(hs, fs, us, tol=cfg.tol, maxit=iters)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    nit = sum(i["iters"] for i in infos)
+    ub = [u.clone() for u in us]
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq_its = 0
+    for H, f, u in zip(hs, fs, us):
+        seq_its += H.solve(f, u, tol=cfg.tol, maxit=iters, hist_cap=0)["iters"]
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(ub, us))
+    for H in hs:
+        H.close()
+    sides = sorted(p["n"] for p in probs)
+    return {"workload": "ellipses64: 64 2D problems, sides " +
+                        "/".join(str(s) for s in sorted(set(sides))) +
+                        " (+2x16 PML), 5 levels 2/8/16/32/64, random-init weights",
+            "precision": precision, "problems": len(probs), "iters_each": iters,
+            "unknowns_total": int(sum((s + 2 * cfg.npml) ** 2 for s in sides)),
+            "iters_per_s": round(nit / el_b, 2), "ms_per_batched_iter": round(el_b / iters * 1e3, 3),
+            "sequential_iters_per_s": round(seq_its / el_s, 2),
+            "speedup_vs_sequential": round((nit / el_b) / (seq_its / el_s), 3),
+            "bitwise_equal_to_sequential": bool(same), "setup_s": round(setup_s, 2)}
+
+
+def served_leg(nreq, rate, seed=3):
+    """The serving workload, scaled to a short run: Poisson arrivals (rate
+    requests/s, seeded) over 16 cached media (12 2D: bump / GRF / ellipses,
+    sides 64-128 + 16-cell PML, the 6-level 2/8/16/32/64/64 model; 4 3D
+    layered media, sides 24-32 + 12-cell PML, the 5-level 2/12/24/48/96
+    model), 1-8 point-source right-hand sides per request, each solved to
+    true relative residual 1e-6 with classical coefficients (random-init
+    weights never converge).  Served: BF16 V-cycle convolutions through the
+    continuous-batching server (HBM budget 200 GB).  Comparator: the plain
+    FP32 path, one right-hand side at a time in arrival order, on the same
+    trace in real time.  Latency = arrival to the request's last solution."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_30495_amd import Handle, Server
+    media = synth.serve_media(seed)
+    trace = synth.serve_trace(media, nreq, rate, seed)
+    models = {2: synth.CONFIGS["grf1024"], 3: synth.CONFIGS["layered192"]}
+    built = []
+    for m in media:
+        mc = models[m["dim"]]
+        tens, feats = synth.shifted_laplacian(m["c"], m["omega"], m["h"], m["npml"], mc.channels,
+                                              mc.nu1, mc.nu2)
+        built.append((mc, synth.pack_blob(m["dim"], mc.channels, mc.nu1, mc.nu2, tens), feats))
+
+    def handle(i, prec):
+        m, (mc, blob, feats) = media[i], built[i]
+        H = Handle(m["c"], m["omega"], m["h"], m["npml"], blob, precision=prec, restart=mc.restart)
+        for l, (a, s) in enumerate(feats, start=1):
+            H.set_features(l, torch.from_numpy(a).cuda(), torch.from_numpy(s).cuda())
+        return H
+
+    fs = [[torch.from_numpy(f).cuda() for f in r["fs"]] for r in trace]
+    nrhs = sum(len(r["fs"]) for r in trace)
+    # served (BF16)
+    srv = Server(hbm_budget=200 << 30)
+    mids = [srv.add_handle(handle(i, "bf16")) for i in range(len(media))]
+    warm = {}
+    for i, m in enumerate(media):          # one warm-up solve per medium
+        warm.setdefault(m["dim"], []).append(i)
+    for dim, idx in warm.items():
+        i = idx[0]
+        f = torch.from_numpy(synth.point_source(media[i]["n"], media[i]["npml"],
+                                                (0.5,) * dim, dim)).cuda()
+        torch.cuda.synchronize()
+        srv.submit(mids[i], [f], [torch.zeros_like(f)], maxit=500)
+    torch.cuda.synchronize()
+    got = 0
+    while got < len(warm):
+        got += len(srv.poll(64, wait_ms=100))
+    us = [[torch.zeros_like(f) for f in r] for r in fs]
+    torch.cuda.synchronize()
+    done, i = {}, 0
+    rid_of = {}
+    t0 = time.perf_counter()
+    while len(done) < nreq:
+        now = time.perf_counter() - t0
+        while i < nreq and trace[i]["t"] <= now:
+            rid_of[srv.submit(mids[trace[i]["medium"]], fs[i], us[i], tol=1e-6, maxit=500)] = i
+            i += 1
+        wait_ms = 20 if i >= nreq else max(0, min(20, int((trace[i]["t"] - now) * 1e3)))
+        for c in srv.poll(64, wait_ms=wait_ms):
+            done[rid_of[c["req_id"]]] = c
+    t_end = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat_s = np.array([done[k]["latency_s"] for k in range(nreq)]) * 1e3
+    ok_s = sum(done[k]["nrhs"] for k in range(nreq) if done[k]["status"] == 0)
+    worst_s = max(done[k]["relres_max"] for k in range(nreq))
+    its_s = sum(done[k]["iters_total"] for k in range(nreq))
+    # plain FP32, one right-hand side at a time, same arrivals
+    hs = [handle(i, "fp32") for i in range(len(media))]
+    u = {k: torch.zeros_like(fs[k][0]) for k in range(nreq)}
+    for dim, idx in warm.items():
+        j = idx[0]
+        f = torch.from_numpy(synth.point_source(media[j]["n"], media[j]["npml"], (0.5,) * dim, dim)).cuda()
+        hs[j].solve(f, torch.zeros_like(f), tol=1e-6, maxit=500, hist_cap=0)
+    torch.cuda.synchronize()
+    lat_p, ok_p, its_p, worst_p = [], 0, 0, 0.0
+    t0 = time.perf_counter()
+    for k, r in enumerate(trace):
+        now = time.perf_counter() - t0
+        if now < r["t"]:
+            time.sleep(r["t"] - now)
+        for f in fs[k]:
+            u[k].zero_()
+            info = hs[r["medium"]].solve(f, u[k], tol=1e-6, maxit=500, hist_cap=0)
+            ok_p += int(info["converged"])
+            its_p += info["iters"]
+            worst_p = max(worst_p, info["relres_true"])
+        lat_p.append(time.perf_counter() - t0 - r["t"])
+    t_end_p = time.perf_counter() - t0
+    for H in hs:
+        H.close()
+    lat_p = np.array(lat_p) * 1e3
+    return {"workload": f"serve: {nreq} Poisson requests at {rate}/s (seed {seed}) over 16 cached "
+                        "media (12 2D sides 64-128, 4 3D sides 24-32), 1-8 rhs each, "
+                        "classical coefficients, tol 1e-6",
+            "rhs": nrhs,
+            "served_bf16": {"solves_per_s": round(ok_s / t_end, 2), "converged": ok_s,
+                            "iters_per_s": round(its_s / t_end, 1),
+                            "p50_ms": round(float(np.percentile(lat_s, 50)), 2),
+                            "p99_ms": round(float(np.percentile(lat_s, 99)), 2),
+                            "max_relres_true": worst_s, "inflight_peak": st["inflight_peak"],
+                            "bytes_peak": st["bytes_peak"], "ticks": st["ticks"],
+                            "rebuilds": st["rebuilds"]},
+            "plain_fp32_one_at_a_time": {"solves_per_s": round(ok_p / t_end_p, 2), "converged": ok_p,
+                                         "iters_per_s": round(its_p / t_end_p, 1),
+                                         "p50_ms": round(float(np.percentile(lat_p, 50)), 2),
+                                         "p99_ms": round(float(np.percentile(lat_p, 99)), 2),
+                                         "max_relres_true": worst_p},
+            "speedup_solves_per_s": round((ok_s / t_end) / max(ok_p / t_end_p, 1e-12), 3)}
+
+
 def traffic_for(kernel):
     """Counter-measured HBM bytes per launch of `kernel` from the committed
     rocprofv3 summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
@@ -248,6 +424,10 @@ def main():
         line["solves"] = [solves_leg(a.precision, a.solves)]
         if not a.single:
             line["solves"].append(solves_leg(other, a.solves))
+    if a.batched_iters > 0:
+        line["batched"] = batched_leg(a.precision, a.batched_iters)
+    if a.serve_requests > 0:
+        line["served"] = served_leg(a.serve_requests, a.serve_rate)
     if cmp_leg is not None:
         line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
                            "ms_per_step": round(cmp_leg["ms_per_step"], 4),

@@ -25,9 +25,10 @@ from .media import (medium_bump, medium_grf, medium_ellipses, medium_layered_sph
                     omega_for_ppw, point_source, gaussian_source, random_rhs, make_problem)
 from .weights import make_weights, pack_blob, weight_names
 from .classical import shifted_laplacian
+from .workloads import make_batch, serve_media, serve_trace
 
 __all__ = [
-    "shifted_laplacian",
+    "shifted_laplacian", "make_batch", "serve_media", "serve_trace",
     "Config", "CONFIGS", "level_sides", "ext_side",
     "medium_bump", "medium_grf", "medium_ellipses", "medium_layered_sphere",
     "omega_for_ppw", "point_source", "gaussian_source", "random_rhs", "make_problem",
