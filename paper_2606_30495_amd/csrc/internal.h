@@ -185,6 +185,7 @@ struct L1Launch {
   float* eo;                  // updated correction (RESID: t = r - A e)
   const float *r, *a, *s;
   L1Weights w;
+  const L1Weights* wdev;      // device copy of w (3D reads the weights through it)
   Dims n;
 };
 hipError_t launch_level1(const L1Launch& l, hipStream_t s);

@@ -19,6 +19,17 @@
 //
 // Variants: FIRST (e = 0: u = s (.) (KS * r), e' = Wsm * u) and RESID
 // (t = r - A e only, the input of the restriction).
+//
+// 3D uses a z-streaming form instead of cube tiles: a block owns a TY x TX
+// column and a chunk of ZC planes and walks it plane by plane, keeping the
+// last planes of e (halo 3 in y and x), t (halo 2) and u (halo 1) in LDS
+// rings.  Each plane of t and u is then computed once per block (a cube
+// tile with a halo of 3 recomputes about four times the work), and only the
+// in-plane halos are shared with neighbouring blocks.  The tap loop runs
+// over dz at run time with the 9 in-plane taps unrolled, so at most one
+// plane's weights are live (the fully unrolled 27-tap form spills).
+#include <type_traits>
+
 #include "internal.h"
 
 namespace mcmg {
@@ -27,7 +38,8 @@ namespace {
 
 template <int D> struct G1;
 template <> struct G1<2> { static constexpr int TZ = 1, TY = 32, TX = 64; };
-template <> struct G1<3> { static constexpr int TZ = 2, TY = 4, TX = 32; };
+// 3D z-streaming tile: TY x TX nodes per plane, ZC planes per block
+struct G3 { static constexpr int TY = 8, TX = 64, ZC = 32; };
 
 constexpr int NTH = 256;
 
@@ -225,6 +237,236 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   }
 }
 
+// Ring slot of plane `pl` (pl >= -4 R) in a ring of R planes.
+__device__ __forceinline__ int ring(int pl, int R) { return (pl + 4 * R) % R; }
+
+template <int VAR>
+__device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __restrict__ wp,
+                                         const int vblk) {
+  constexpr int TY = G3::TY, TX = G3::TX, ZC = G3::ZC;
+  constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // y-x halo of the staged e
+  constexpr int EY = TY + 2 * H, EX = TX + 2 * H, NE = EY * EX;
+  constexpr int NER = (VAR == L1_STEP) ? 4 : 3;          // e ring (STEP keeps e of the output plane)
+  constexpr int TYt = TY + 4, TXt = TX + 4, NT = TYt * TXt;
+  constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
+  constexpr int NO = TY * TX;
+  constexpr int PE = (NE + NTH - 1) / NTH, PT = (NT + NTH - 1) / NTH;
+  constexpr int PU = (NU + NTH - 1) / NTH, PO = (NO + NTH - 1) / NTH;
+  __shared__ float2 se[(VAR == L1_FIRST) ? 1 : NER * NE];
+  __shared__ float2 st[(VAR == L1_RESID) ? 1 : 3 * NT];
+  __shared__ float2 su[(VAR == L1_RESID) ? 1 : 3 * NU];
+
+  const float2* __restrict__ e = reinterpret_cast<const float2*>(A.e);
+  float2* __restrict__ eo = reinterpret_cast<float2*>(A.eo);
+  const float2* __restrict__ r = reinterpret_cast<const float2*>(A.r);
+  const float2* __restrict__ a = reinterpret_cast<const float2*>(A.a);
+  const float2* __restrict__ s = reinterpret_cast<const float2*>(A.s);
+  const int NZ = A.n.n[0], NY = A.n.n[1], NX = A.n.n[2];
+  const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
+  const int per = (ntiles + 7) / 8;
+  const int tl = (vblk % 8) * per + vblk / 8;   // XCD-contiguous bands
+  if (tl >= ntiles) return;
+  const int x0 = (tl % A.tiles_x) * TX, y0 = ((tl / A.tiles_x) % A.tiles_y) * TY;
+  const int zb = (tl / (A.tiles_x * A.tiles_y)) * ZC;
+  const int ze = min(zb + ZC, NZ);
+  auto inside = [&](int z, int y, int x) {
+    return x >= 0 && x < NX && y >= 0 && y < NY && z >= 0 && z < NZ;
+  };
+  auto gidx = [&](int z, int y, int x) { return ((long long)z * NY + y) * NX + x; };
+  const float2 zero = make_float2(0.f, 0.f);
+
+  // e plane k on the e box (zero outside the grid)
+  auto load_e = [&](int k) {
+    float2 v[PE];
+#pragma unroll
+    for (int j = 0; j < PE; ++j) {
+      const int i = threadIdx.x + j * NTH;
+      const int y = i / EX, x = i % EX;
+      const int gy = y0 - H + y, gx = x0 - H + x;
+      v[j] = (i < NE && inside(k, gy, gx)) ? e[gidx(k, gy, gx)] : zero;
+    }
+    float2* dst = se + ring(k, NER) * NE;
+#pragma unroll
+    for (int j = 0; j < PE; ++j) {
+      const int i = threadIdx.x + j * NTH;
+      if (i < NE) dst[i] = v[j];
+    }
+  };
+  // acc += (X * src)[point] over the 27 taps, src planes q-1, q, q+1 in a ring
+  // (2 x 2 channel block X of the weight set `off` = W, KA, KS or Wsm).
+  auto conv2 = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
+                   const float* Xw, const int* base, float* c0, float* c1, auto npts) {
+    constexpr int NP = decltype(npts)::value;
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz) {
+      const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
+      const float* w = Xw + dz * 9;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
+        const float a00 = w[t], a01 = w[27 + t], a10 = w[54 + t], a11 = w[81 + t];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const float2 v = P[base[k] + to];
+          c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
+          c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+        }
+      }
+    }
+  };
+  // t plane q on the t box (halo 2): t = r - W*e - a (.) (KA*e); FIRST: t = r
+  auto make_t = [&](int q) {
+    float2 rv[PT], av[PT];
+    int eb[PT];
+    bool ok[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / TXt, x = i % TXt;
+      const int gy = y0 - 2 + y, gx = x0 - 2 + x;
+      ok[k] = i < NT && inside(q, gy, gx);
+      rv[k] = ok[k] ? r[gidx(q, gy, gx)] : zero;
+      av[k] = (ok[k] && VAR != L1_FIRST) ? a[gidx(q, gy, gx)] : zero;
+      eb[k] = (i < NT) ? (y + H - 2) * EX + (x + H - 2) : EX + 1;
+    }
+    float w0[PT], w1[PT], k0[PT], k1[PT];
+#pragma unroll
+    for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
+    if (VAR != L1_FIRST) {
+      conv2(se, NER, NE, q, EX, &wp->W[0][0][0], eb, w0, w1, std::integral_constant<int, PT>());
+      conv2(se, NER, NE, q, EX, &wp->KA[0][0][0], eb, k0, k1, std::integral_constant<int, PT>());
+    }
+    float2* dst = st + ring(q, 3) * NT;
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NT)
+        dst[i] = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
+                       : zero;
+    }
+  };
+  // u plane p on the u box (halo 1): u = s (.) (KS * t)
+  auto make_u = [&](int p) {
+    float2 sv[PU];
+    int tb[PU];
+    bool ok[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / UX, x = i % UX;
+      const int gy = y0 - 1 + y, gx = x0 - 1 + x;
+      ok[k] = i < NU && inside(p, gy, gx);
+      sv[k] = ok[k] ? s[gidx(p, gy, gx)] : zero;
+      tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
+    }
+    float c0[PU], c1[PU];
+#pragma unroll
+    for (int k = 0; k < PU; ++k) c0[k] = c1[k] = 0.f;
+    conv2(st, 3, NT, p, TXt, &wp->KS[0][0][0], tb, c0, c1, std::integral_constant<int, PU>());
+    float2* dst = su + ring(p, 3) * NU;
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NU) dst[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
+    }
+  };
+  // output plane z: e' = e + Wsm * u
+  auto make_out = [&](int z) {
+    int ub[PO];
+    bool ok[PO];
+#pragma unroll
+    for (int k = 0; k < PO; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / TX, x = i % TX;
+      ok[k] = i < NO && inside(z, y0 + y, x0 + x);
+      ub[k] = (i < NO) ? (y + 1) * UX + (x + 1) : UX + 1;
+    }
+    float c0[PO], c1[PO];
+#pragma unroll
+    for (int k = 0; k < PO; ++k) c0[k] = c1[k] = 0.f;
+    conv2(su, 3, NU, z, UX, &wp->Wsm[0][0][0], ub, c0, c1, std::integral_constant<int, PO>());
+#pragma unroll
+    for (int k = 0; k < PO; ++k) {
+      if (!ok[k]) continue;
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / TX, x = i % TX;
+      float2 ev = zero;
+      if (VAR == L1_STEP) ev = se[ring(z, NER) * NE + (y + H) * EX + (x + H)];
+      eo[gidx(z, y0 + y, x0 + x)] = make_float2(ev.x + c0[k], ev.y + c1[k]);
+    }
+  };
+
+  if (VAR == L1_RESID) {
+    // t = r - W*e - a (.) (KA*e) on the tile, e planes z-1..z+1 (halo 1)
+    for (int k = zb - 1; k <= ze; ++k) {
+      load_e(k);
+      __syncthreads();
+      const int z = k - 1;
+      if (z >= zb) {
+        int eb[PO];
+        bool ok[PO];
+        float2 rv[PO], av[PO];
+#pragma unroll
+        for (int j = 0; j < PO; ++j) {
+          const int i = threadIdx.x + j * NTH;
+          const int y = i / TX, x = i % TX;
+          ok[j] = i < NO && inside(z, y0 + y, x0 + x);
+          rv[j] = ok[j] ? r[gidx(z, y0 + y, x0 + x)] : zero;
+          av[j] = ok[j] ? a[gidx(z, y0 + y, x0 + x)] : zero;
+          eb[j] = (i < NO) ? (y + 1) * EX + (x + 1) : EX + 1;
+        }
+        float w0[PO], w1[PO], k0[PO], k1[PO];
+#pragma unroll
+        for (int j = 0; j < PO; ++j) w0[j] = w1[j] = k0[j] = k1[j] = 0.f;
+        conv2(se, NER, NE, z, EX, &wp->W[0][0][0], eb, w0, w1, std::integral_constant<int, PO>());
+        conv2(se, NER, NE, z, EX, &wp->KA[0][0][0], eb, k0, k1, std::integral_constant<int, PO>());
+#pragma unroll
+        for (int j = 0; j < PO; ++j) {
+          if (!ok[j]) continue;
+          const int i = threadIdx.x + j * NTH;
+          const int y = i / TX, x = i % TX;
+          eo[gidx(z, y0 + y, x0 + x)] = make_float2(rv[j].x - w0[j] - av[j].x * k0[j],
+                                                    rv[j].y - w1[j] - av[j].y * k1[j]);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+  // STEP: at k, e plane k arrives, t plane k-1, u plane k-2, output plane k-3.
+  // FIRST: t plane k (= r), u plane k-1, output plane k-2.
+  constexpr int LAG = (VAR == L1_STEP) ? 1 : 0;
+  for (int k = zb - 2 - LAG; k <= ze + 1 + LAG; ++k) {
+    if (VAR == L1_STEP) {
+      load_e(k);
+      __syncthreads();
+    }
+    const int q = k - LAG, p = q - 1, z = q - 2;
+    if (q >= zb - 2) make_t(q);
+    __syncthreads();
+    if (p >= zb - 1) make_u(p);
+    __syncthreads();
+    if (z >= zb) make_out(z);
+    __syncthreads();
+  }
+}
+
+template <int VAR>
+__global__ __launch_bounds__(NTH) void l1z_kernel(L1Args A) {
+  l1z_body<VAR>(A, A.wp, blockIdx.x);
+}
+
+template <int VAR>
+__global__ __launch_bounds__(NTH) void l1z_kernel_batched(const L1Args* __restrict__ tab,
+                                                          const int* __restrict__ pre, int np,
+                                                          const int* __restrict__ frozen,
+                                                          const int* __restrict__ row) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const L1Args A = tab[batch_entry(row, np, p)];
+  l1z_body<VAR>(A, A.wp, blockIdx.x - pre[p]);
+}
+
 template <int D, int VAR>
 __global__ __launch_bounds__(NTH) void l1_kernel(L1Args A, L1Weights w) {
   l1_body<D, VAR>(A, w, blockIdx.x);
@@ -244,13 +486,25 @@ __global__ __launch_bounds__(NTH) void l1_kernel_batched(const L1Args* __restric
 
 template <int D, int VAR>
 hipError_t run(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
-  if (b) {
-    hipLaunchKernelGGL((l1_kernel_batched<D, VAR>), dim3(b->total), dim3(NTH), 0, s,
-                       (const L1Args*)b->tab, b->pre, b->np, b->frozen, b->row);
+  if constexpr (D == 3) {
+    if (b) {
+      hipLaunchKernelGGL((l1z_kernel_batched<VAR>), dim3(b->total), dim3(NTH), 0, s,
+                         (const L1Args*)b->tab, b->pre, b->np, b->frozen, b->row);
+    } else {
+      if (!l.wdev) return hipErrorInvalidValue;
+      int nblk;
+      const L1Args A = l1_args(l, l.wdev, &nblk);
+      hipLaunchKernelGGL((l1z_kernel<VAR>), dim3(nblk), dim3(NTH), 0, s, A);
+    }
   } else {
-    int nblk;
-    const L1Args A = l1_args(l, nullptr, &nblk);
-    hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(nblk), dim3(NTH), 0, s, A, l.w);
+    if (b) {
+      hipLaunchKernelGGL((l1_kernel_batched<D, VAR>), dim3(b->total), dim3(NTH), 0, s,
+                         (const L1Args*)b->tab, b->pre, b->np, b->frozen, b->row);
+    } else {
+      int nblk;
+      const L1Args A = l1_args(l, nullptr, &nblk);
+      hipLaunchKernelGGL((l1_kernel<D, VAR>), dim3(nblk), dim3(NTH), 0, s, A, l.w);
+    }
   }
   return hipGetLastError();
 }
@@ -275,8 +529,8 @@ hipError_t dispatch(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
 }  // namespace
 
 L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk) {
-  const int TX = l.dim == 2 ? G1<2>::TX : G1<3>::TX, TY = l.dim == 2 ? G1<2>::TY : G1<3>::TY;
-  const int TZ = l.dim == 2 ? G1<2>::TZ : G1<3>::TZ;
+  const int TX = l.dim == 2 ? G1<2>::TX : G3::TX, TY = l.dim == 2 ? G1<2>::TY : G3::TY;
+  const int TZ = l.dim == 2 ? G1<2>::TZ : G3::ZC;
   const int NX = (l.dim == 2) ? l.n.n[1] : l.n.n[2], NY = (l.dim == 2) ? l.n.n[0] : l.n.n[1];
   const int NZ = (l.dim == 2) ? 1 : l.n.n[0];
   L1Args A;

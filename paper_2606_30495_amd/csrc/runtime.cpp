@@ -300,6 +300,7 @@ hipError_t Ctx::level1(Level& lv, int var, int step) {
   l.eo = var == L1_RESID ? lv.t : lv.e_alt;
   l.r = lv.r; l.a = lv.a; l.s = lv.s;
   l.w = lv.l1w[var == L1_RESID ? 0 : step];
+  l.wdev = lv.l1w_dev[var == L1_RESID ? 0 : step];
   l.n = lv.dims;
   hipError_t e;
   if (rec) {

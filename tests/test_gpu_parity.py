@@ -16,6 +16,8 @@ CASES = {
     "ragged2d": (2, 37, 5, (2, 8, 16, 32)),       # 47 -> 24 -> 12 -> 6: odd and even sides
     "small3d": (3, 14, 3, (2, 4, 8)),             # 20 -> 10 -> 5
     "ragged3d": (3, 11, 2, (2, 12, 24)),          # 15 -> 8 -> 4
+    # 70^3: several z-chunks of the streaming level-1 sweep, ragged in z, y, x
+    "chunked3d": (3, 64, 3, (2, 4, 8)),
 }
 
 
