@@ -10,6 +10,7 @@ struct MfmaConv {
   int mode;              // CONV_S1 / CONV_S2 (restriction) / CONV_T2 (prolongation)
   int epi;               // EPI_SET / EPI_ADD / EPI_MUL / EPI_RESID
   int mt, ntw;           // tile: 16*mt output nodes per wave row, ntw column tiles per block
+  int rpw;               // node rows per wave (block = 4 * rpw rows along y, z)
   int kchunk;            // K-steps per weight chunk staged in LDS
   const float* x;        // input [in nodes][cin] float32
   const void* wA;        // packed [4*nsteps][ncols][KV] (bf16 or float32)
@@ -44,7 +45,10 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
 // Padded sizes of the packed operands (see conv_mfma.hip for the layout).
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
                     int* npairs, int* nsteps);
-size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int cinp, int epi, int kchunk);
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
+                      int kchunk);
+// Whether a tile (mt, ntw, rpw) is instantiated for this dim / epilogue.
+bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw);
 hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s);
 const char* mfma_kernel_name(const MfmaConv& a);
 

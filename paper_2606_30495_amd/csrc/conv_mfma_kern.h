@@ -1,0 +1,414 @@
+// Kernel templates of the matrix-core convolutions (included by the
+// per-(dim, precision, mode group) instantiation units conv_mfma_i*.hip; the
+// algorithm is described in conv_mfma.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <type_traits>
+
+#include "conv_mfma.h"
+#include "internal.h"
+
+namespace mcmg {
+
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16;
+
+__device__ __forceinline__ u16 f2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (u16)(u >> 16);
+}
+
+// Output tile and staged input tile geometry per (D, MODE, MT, RPW): the
+// block's 4 * RPW GEMM rows (node rows along y, z) are split over its 4
+// waves, row rho = wave + 4 i (i < RPW); each row holds 16 * MT nodes in x.
+template <int D, int MODE, int MT, int RPW>
+struct Geo {
+  static constexpr int TX = 16 * MT;
+  static constexpr int ROWS = 4 * RPW;
+  static constexpr int TY = (D == 2) ? ROWS : (RPW == 1 ? 2 : 4);
+  static constexpr int TZ = (D == 2) ? 1 : ROWS / TY;
+  // staged tile extent per axis
+  static constexpr int ext(int t) { return MODE == CONV_S1 ? t + 2 : (MODE == CONV_S2 ? 2 * t + 1 : t + 1); }
+  static constexpr int HX = ext(TX), HY = ext(TY), HZ = (D == 2) ? 1 : ext(TZ);
+  static constexpr int NODES = HX * HY * HZ;
+  static constexpr int TAPS = (MODE == CONV_T2) ? ((D == 2) ? 4 : 8) : ((D == 2) ? 9 : 27);
+  static constexpr int W = (MODE == CONV_T2) ? 2 : 3;   // window per axis
+};
+
+template <bool BF> constexpr int KVOF() { return BF ? 8 : 1; }
+
+// Tile shapes that are instantiated: accumulators (NACC * RPW * MT * NTW
+// 16x16 tiles) within 16, RPW up to 2 in 2D and 4 in 3D.
+template <int D, int EPI, int MT, int NTW, int RPW>
+constexpr bool tile_ok() {
+  return ((EPI == EPI_RESID) ? 2 : 1) * RPW * MT * NTW <= 16 && RPW <= ((D == 2) ? 2 : 4);
+}
+
+// One block of the convolution: `vblk` is the block index inside this
+// problem's grid (the batched wrapper maps the launch's blocks onto problems).
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
+__device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
+  const float* __restrict__ x = A.x;
+  const void* __restrict__ wA = A.wA;
+  const void* __restrict__ wB = A.wB;
+  float* __restrict__ y = A.y;
+  const float* __restrict__ r = A.r;
+  const float* __restrict__ feat = A.feat;
+  const int cin = A.cin, cinp = A.cinp, cout = A.cout, ncols = A.ncols, nsteps = A.nsteps;
+  const int npairs = A.npairs, tiles_x = A.tiles_x, tiles_y = A.tiles_y, tiles_z = A.tiles_z;
+  const int kchunk = A.kchunk;
+  const Dims in = A.in, out = A.out;
+  using G = Geo<D, MODE, MT, RPW>;
+  constexpr int KV = KVOF<BF>();
+  constexpr int NACC = (EPI == EPI_RESID) ? 2 : 1;
+  constexpr int ES = BF ? 2 : 4;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int stride = cinp + (BF ? 8 : 1);  // LDS node stride (elements)
+  unsigned char* bsm = smem + (((size_t)G::NODES * stride * ES + 15) / 16) * 16;
+  constexpr int BROW = NTW * 16 * KV;      // elements of one pair row in the chunk
+  constexpr int V16 = BROW * ES / 16;      // 16-byte vectors per row
+
+  const int ntiles = tiles_x * tiles_y * tiles_z;
+  const int per = (ntiles + 7) / 8;
+  const int tl = (vblk % 8) * per + vblk / 8;
+  if (tl >= ntiles) return;
+  const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, tz = tl / (tiles_x * tiles_y);
+  const int x0 = tx * G::TX, y0 = ty * G::TY, z0 = tz * G::TZ;
+  const int col0 = blockIdx.y * NTW * 16;
+  // grids: 2D (n[0] rows, n[1] x), 3D (n[0] z, n[1] y, n[2] x)
+  const int IX = (D == 2) ? in.n[1] : in.n[2], IY = (D == 2) ? in.n[0] : in.n[1];
+  const int IZ = (D == 2) ? 1 : in.n[0];
+  const int OX = (D == 2) ? out.n[1] : out.n[2], OY = (D == 2) ? out.n[0] : out.n[1];
+  const int OZ = (D == 2) ? 1 : out.n[0];
+  // origin of the staged tile in input coordinates
+  int sx, sy, sz;
+  if (MODE == CONV_S1) { sx = x0 - 1; sy = y0 - 1; sz = z0 - 1; }
+  else if (MODE == CONV_S2) { sx = 2 * x0 - 1; sy = 2 * y0 - 1; sz = 2 * z0 - 1; }
+  else { sx = x0; sy = y0; sz = z0; }
+  if (D == 2) sz = 0;
+
+  // weight chunk [s0, s0 + ks): rows q in [4 s0, 4 (s0 + ks)), columns [col0, col0 + 16 NTW)
+  auto wsrc = [&](int s0, int ks, int idx) {
+    const int nrow = 4 * ks;
+    const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
+    const int row = rem / V16, vv = rem % V16;
+    return reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(a ? wB : wA) +
+                                          (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES +
+                                          (size_t)vv * 16);
+  };
+  auto wdst = [&](int ks, int idx) {
+    const int nrow = 4 * ks;
+    const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
+    const int row = rem / V16, vv = rem % V16;
+    return reinterpret_cast<uint4*>(bsm + (((size_t)a * 4 * kchunk + row) * BROW) * ES + (size_t)vv * 16);
+  };
+  // The first weight chunk is fetched together with the input tile when it
+  // fits in WB vectors per thread: one memory latency for both.
+  constexpr int WB = 4;
+  const int ks0 = nsteps < kchunk ? nsteps : kchunk;
+  const int wtot0 = NACC * 4 * ks0 * V16;
+  const bool wpre = wtot0 <= 256 * WB;
+  uint4 wv[WB];
+  if (wpre) {
+#pragma unroll
+    for (int k = 0; k < WB; ++k) {
+      const int idx = threadIdx.x + k * 256;
+      if (idx < wtot0) wv[k] = *wsrc(0, ks0, idx);
+    }
+  }
+
+  // ---- stage the input tile: loads are issued in batches of SB per thread
+  // before any LDS store, so a block waits for one memory latency per batch
+  {
+    constexpr int SB = 8;
+    const bool vec4 = (cin % 4) == 0;
+    const int ng = cinp / 4;
+    const int total = G::NODES * ng;
+    for (int base = threadIdx.x; base < total; base += 256 * SB) {
+      float4 v[SB];
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        const int hx = node % G::HX, hy = (node / G::HX) % G::HY, hz = node / (G::HX * G::HY);
+        const int gx = sx + hx, gy = sy + hy, gz = sz + hz;
+        if (gx >= 0 && gx < IX && gy >= 0 && gy < IY && gz >= 0 && gz < IZ && c < cin) {
+          const long long g = (((long long)gz * IY + gy) * IX + gx) * cin;
+          if (vec4) {
+            v[k] = *reinterpret_cast<const float4*>(x + g + c);
+          } else {
+            v[k].x = x[g + c];
+            if (c + 1 < cin) v[k].y = x[g + c + 1];
+            if (c + 2 < cin) v[k].z = x[g + c + 2];
+            if (c + 3 < cin) v[k].w = x[g + c + 3];
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        if constexpr (BF) {
+          u16* s = reinterpret_cast<u16*>(smem) + (size_t)node * stride + c;
+          s[0] = f2bf(v[k].x); s[1] = f2bf(v[k].y); s[2] = f2bf(v[k].z); s[3] = f2bf(v[k].w);
+        } else {
+          float* s = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
+          s[0] = v[k].x; s[1] = v[k].y; s[2] = v[k].z; s[3] = v[k].w;
+        }
+      }
+    }
+  }
+  if (wpre) {
+#pragma unroll
+    for (int k = 0; k < WB; ++k) {
+      const int idx = threadIdx.x + k * 256;
+      if (idx < wtot0) *wdst(ks0, idx) = wv[k];
+    }
+  }
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+
+  floatx4 acc[NACC][RPW][MT][NTW];
+#pragma unroll
+  for (int a = 0; a < NACC; ++a)
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) acc[a][i][m][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int cpv = cinp / KV;
+  const int KS = kchunk;
+  for (int s0 = 0; s0 < nsteps; s0 += KS) {
+    const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
+    if (s0 > 0 || !wpre) {
+      __syncthreads();   // previous chunk consumed (and input tile staged)
+      constexpr int SB = 8;
+      const int total = NACC * 4 * ks * V16;
+      for (int base = threadIdx.x; base < total; base += 256 * SB) {
+        uint4 v[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          if (idx < total) v[k] = *wsrc(s0, ks, idx);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          if (idx < total) *wdst(ks, idx) = v[k];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll 2
+    for (int ss = 0; ss < ks; ++ss) {
+      const int s = s0 + ss;
+      int q = 4 * s + lg;
+      if (q >= npairs) q = npairs - 1;   // weight rows are zero there
+      const int tap = q / cpv, cb = q - tap * cpv;
+      int dz = 0, dy, dx;
+      if (D == 2) { dy = tap / G::W; dx = tap % G::W; }
+      else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
+      typename std::conditional<BF, bf16x8, float>::type bf[NACC][NTW];
+#pragma unroll
+      for (int a = 0; a < NACC; ++a)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t) {
+          const size_t o = ((size_t)a * 4 * KS + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
+          if constexpr (BF) bf[a][t] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(bsm) + o);
+          else bf[a][t] = reinterpret_cast<const float*>(bsm)[o];
+        }
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int rho = wave + 4 * i;
+        const int wy = rho % G::TY, wz = rho / G::TY;
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const int ox = m * 16 + li;   // output x inside the tile
+          int hx, hy, hz;
+          if (MODE == CONV_S2) { hx = 2 * ox + dx; hy = 2 * wy + dy; hz = 2 * wz + dz; }
+          else { hx = ox + dx; hy = wy + dy; hz = wz + dz; }
+          const size_t node = ((size_t)hz * G::HY + hy) * G::HX + hx;
+          if constexpr (BF) {
+            const bf16x8 af = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) +
+                                                               node * stride + cb * KV);
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+#pragma unroll
+              for (int a = 0; a < NACC; ++a)
+                acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[a][t], acc[a][i][m][t], 0, 0, 0);
+          } else {
+            const float af = reinterpret_cast<const float*>(smem)[node * stride + cb];
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+#pragma unroll
+              for (int a = 0; a < NACC; ++a)
+                acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[a][t], acc[a][i][m][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+
+  // ---- epilogue: per (row, m) the operands of all its outputs are loaded
+  // first, then combined and stored
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int rho = wave + 4 * i;
+    const int gy = y0 + rho % G::TY, gz = z0 + rho / G::TY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      long long o[NTW][4];
+      float e0[NTW][4], e1[NTW][4];
+#pragma unroll
+      for (int t = 0; t < NTW; ++t) {
+        const int col = col0 + t * 16 + li;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int gx = x0 + m * 16 + 4 * lg + rr;
+          o[t][rr] = -1;
+          if (MODE == CONV_T2) {
+            // column = class * cout + c; class bits: x fastest
+            const int cls = col / cout, c = col - cls * cout;
+            const int ax = cls & 1, ay = (cls >> 1) & 1, az = (D == 3) ? ((cls >> 2) & 1) : 0;
+            const int fx = 2 * gx + ax, fy = 2 * gy + ay, fz = (D == 3) ? 2 * gz + az : 0;
+            if (cls < (1 << D) && fx < OX && fy < OY && fz < OZ)
+              o[t][rr] = (((long long)fz * OY + fy) * OX + fx) * cout + c;
+          } else {
+            if (col < cout && gx < OX && gy < OY && gz < OZ)
+              o[t][rr] = (((long long)gz * OY + gy) * OX + gx) * cout + col;
+          }
+          e0[t][rr] = 0.f;
+          e1[t][rr] = 0.f;
+          if (o[t][rr] >= 0) {
+            if (EPI == EPI_ADD) e0[t][rr] = y[o[t][rr]];
+            else if (EPI == EPI_MUL) e0[t][rr] = feat[o[t][rr]];
+            else if (EPI == EPI_RESID) { e0[t][rr] = r[o[t][rr]]; e1[t][rr] = feat[o[t][rr]]; }
+          }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NTW; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          if (o[t][rr] < 0) continue;
+          float v = acc[0][i][m][t][rr];
+          if (EPI == EPI_ADD) v = e0[t][rr] + v;
+          else if (EPI == EPI_MUL) v = e0[t][rr] * v;
+          else if (EPI == EPI_RESID) v = e0[t][rr] - v - e1[t][rr] * acc[NACC - 1][i][m][t][rr];
+          y[o[t][rr]] = v;
+        }
+    }
+  }
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
+__global__ __launch_bounds__(256) void mconv_kernel(MArgs A) {
+  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, blockIdx.x);
+}
+
+// Batched form: one launch for several problems; pre[p] is the first block of
+// problem p (pre[np] = total blocks), tab[p] its arguments.
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
+__global__ __launch_bounds__(256) void mconv_kernel_batched(const MArgs* __restrict__ tab,
+                                                            const int* __restrict__ pre, int np,
+                                                            const int* __restrict__ frozen,
+                                                            const int* __restrict__ row) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const MArgs A = tab[batch_entry(row, np, p)];
+  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, blockIdx.x - pre[p]);
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
+hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  if constexpr (!tile_ok<D, EPI, MT, NTW, RPW>()) {
+    return hipErrorInvalidValue;
+  } else {
+    const int nslices = a.ncols / (16 * NTW);
+    const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.rpw, a.cinp, a.epi, a.kchunk);
+    if (b) {
+      hipLaunchKernelGGL((mconv_kernel_batched<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(b->total, nslices),
+                         dim3(256), lds, s, (const MArgs*)b->tab, b->pre, b->np, b->frozen, b->row);
+    } else {
+      int nblk;
+      const MArgs A = mfma_args(a, &nblk);
+      hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(nblk, nslices), dim3(256),
+                         lds, s, A);
+    }
+    return hipGetLastError();
+  }
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT, int NTW>
+hipError_t by_rpw(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  switch (a.rpw) {
+    case 1: return run<D, BF, MODE, EPI, MT, NTW, 1>(a, b, s);
+    case 2: return run<D, BF, MODE, EPI, MT, NTW, 2>(a, b, s);
+    case 4: return run<D, BF, MODE, EPI, MT, NTW, 4>(a, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF, int MODE, int EPI, int MT>
+hipError_t by_ntw(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  switch (a.ntw) {
+    case 1: return by_rpw<D, BF, MODE, EPI, MT, 1>(a, b, s);
+    case 2: return by_rpw<D, BF, MODE, EPI, MT, 2>(a, b, s);
+    case 4: return by_rpw<D, BF, MODE, EPI, MT, 4>(a, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF, int MODE, int EPI>
+hipError_t by_mt(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  switch (a.mt) {
+    case 1: return by_ntw<D, BF, MODE, EPI, 1>(a, b, s);
+    case 2: return by_ntw<D, BF, MODE, EPI, 2>(a, b, s);
+    case 4: return by_ntw<D, BF, MODE, EPI, 4>(a, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF>
+hipError_t by_mode_s1(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  if (a.mode != CONV_S1) return hipErrorInvalidValue;
+  switch (a.epi) {
+    case EPI_SET: return by_mt<D, BF, CONV_S1, EPI_SET>(a, b, s);
+    case EPI_ADD: return by_mt<D, BF, CONV_S1, EPI_ADD>(a, b, s);
+    case EPI_MUL: return by_mt<D, BF, CONV_S1, EPI_MUL>(a, b, s);
+    case EPI_RESID: return by_mt<D, BF, CONV_S1, EPI_RESID>(a, b, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, bool BF>
+hipError_t by_mode_st(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  if (a.mode == CONV_S2 && a.epi == EPI_SET) return by_mt<D, BF, CONV_S2, EPI_SET>(a, b, s);
+  if (a.mode == CONV_T2 && a.epi == EPI_ADD) return by_mt<D, BF, CONV_T2, EPI_ADD>(a, b, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+}  // namespace mcmg
+
+// One instantiation unit: NAME runs dimension D, precision BF, mode group
+// GROUP (s1: stride-1 convolutions; st: restriction and prolongation).
+#define MCONV_UNIT(NAME, D, BF, GROUP)                                                   \
+  namespace mcmg {                                                                        \
+  hipError_t NAME(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {              \
+    return by_mode_##GROUP<D, BF>(a, b, s);                                               \
+  }                                                                                       \
+  }

@@ -172,6 +172,7 @@ mcmg_status Engine::build() {
           MfmaConv a = works_[i]->ops[r][q].mf;
           a.mt = ot.proto.mf.mt;      // one tile shape for the whole launch
           a.ntw = ot.proto.mf.ntw;
+          a.rpw = ot.proto.mf.rpw;
           a.kchunk = ot.proto.mf.kchunk;
           int nblk;
           tab[(size_t)r * np + i] = mfma_args(a, &nblk);

@@ -4,14 +4,17 @@
 //
 // Autotuner: for every convolution instance (mode, epilogue, channels, grid)
 // the candidate tiles (16*mt nodes per wave row, mt in {1,2,4}; ntw column
-// tiles per block, ntw in {1,2,4}) that fit the LDS are each launched on the
-// handle's own buffers and timed with HIP events; the fastest is kept.
+// tiles per block, ntw in {1,2,4}; rpw node rows per wave, rpw in {1,2} in
+// 2D and {1,2,4} in 3D) that fit the LDS are each launched on the handle's
+// own buffers and timed with HIP events; the fastest is kept.
 // Choices are cached per process and, when MCMG_TUNE_CACHE names a file, in
-// that JSON file ({"key": [mt, ntw], ...}), keyed by
+// that JSON file ({"key": [mt, ntw, rpw], ...}; two numbers read as rpw 1), keyed by
 // arch|dim|precision|mode|epi|cin|cout|grid.  Without MCMG_TUNE_CACHE the
 // table tune_gfx950.json next to libmcmg.so (written by an earlier tuning
 // run) is read, so shapes it covers get the same tiles in every process.
 // MCMG_AUTOTUNE=0 skips timing and takes the first fitting candidate.
+// MCMG_FORCE_TILE=mt,ntw,rpw takes that tile wherever it is a candidate
+// (tests use it to run every tile shape against the oracle).
 #include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
@@ -34,7 +37,11 @@ namespace mcmg {
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;
+struct Tile {
+  int mt, ntw, rpw;
+  bool operator==(const Tile& o) const { return mt == o.mt && ntw == o.ntw && rpw == o.rpw; }
+};
+std::map<std::string, Tile> g_tune;
 bool g_tune_loaded = false;
 
 const char* cache_path() {
@@ -67,12 +74,11 @@ void load_cache_locked() {
     const size_t j = s.find('"', i + 1);
     if (j == std::string::npos) break;
     const std::string key = s.substr(i + 1, j - i - 1);
-    int mt = 0, ntw = 0;
+    int mt = 0, ntw = 0, rpw = 1;
     const size_t b = s.find('[', j);
     if (b == std::string::npos) break;
-    if (sscanf(s.c_str() + b, "[%d,%d]", &mt, &ntw) == 2 ||
-        sscanf(s.c_str() + b, "[%d, %d]", &mt, &ntw) == 2)
-      g_tune[key] = {mt, ntw};
+    const int got = sscanf(s.c_str() + b, "[%d ,%d ,%d", &mt, &ntw, &rpw);
+    if (got >= 2) g_tune[key] = {mt, ntw, got == 3 ? rpw : 1};
     i = s.find(']', b);
     if (i == std::string::npos) break;
   }
@@ -86,8 +92,8 @@ void save_cache_locked() {
   f << "{\n";
   size_t k = 0;
   for (auto& kv : g_tune) {
-    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
-      << (++k < g_tune.size() ? ",\n" : "\n");
+    f << "  \"" << kv.first << "\": [" << kv.second.mt << ", " << kv.second.ntw << ", "
+      << kv.second.rpw << "]" << (++k < g_tune.size() ? ",\n" : "\n");
   }
   f << "}\n";
 }
@@ -146,7 +152,8 @@ hipError_t Ctx::run_mop(const MOp& op, const float* x, const void* wA, const voi
   MfmaConv a;
   a.dim = dim;
   a.bf16 = precision == MCMG_BF16 ? 1 : 0;
-  a.mode = op.mode; a.epi = op.epi; a.mt = op.mt; a.ntw = op.ntw; a.kchunk = op.kchunk;
+  a.mode = op.mode; a.epi = op.epi; a.mt = op.mt; a.ntw = op.ntw; a.rpw = op.rpw;
+  a.kchunk = op.kchunk;
   a.x = x; a.wA = wA; a.wB = wB; a.y = y; a.r = r; a.feat = feat;
   a.cin = op.cin; a.cinp = op.cinp; a.cout = op.cout; a.ncols = op.ncols;
   a.nsteps = op.nsteps; a.npairs = op.npairs;
@@ -226,24 +233,30 @@ mcmg_status Ctx::plan_mfma() {
   };
   // weight chunk: all K-steps at once when the LDS allows (one load latency
   // per block), else halve until it fits
-  auto kchunk_for = [&](const MOp& op, int mt, int ntw) {
+  auto kchunk_for = [&](const MOp& op, const Tile& t) {
     int kc = op.nsteps;
-    while (kc > 1 && mfma_lds_bytes(dim, bf, op.mode, mt, ntw, op.cinp, op.epi, kc) > 96 * 1024)
+    while (kc > 1 && mfma_lds_bytes(dim, bf, op.mode, t.mt, t.ntw, t.rpw, op.cinp, op.epi, kc) > 96 * 1024)
       kc = (kc + 1) / 2;
     return kc;
   };
   // candidate tiles that fit, in a fixed preference order
   auto candidates = [&](const MOp& op) {
-    std::vector<std::pair<int, int>> c;
+    std::vector<Tile> c;
     const int nt = op.ncols / 16;
-    for (int mt : {2, 4, 1})
-      for (int ntw : {1, 2, 4}) {
-        if (nt % ntw) continue;
-        const int kc = kchunk_for(op, mt, ntw);
-        if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, op.cinp, op.epi, kc) > lds_max) continue;
-        c.push_back({mt, ntw});
-      }
+    for (int rpw : {1, 2, 4})
+      for (int mt : {2, 4, 1})
+        for (int ntw : {1, 2, 4}) {
+          if (nt % ntw || !mfma_tile_ok(dim, op.epi, mt, ntw, rpw)) continue;
+          const Tile t{mt, ntw, rpw};
+          const int kc = kchunk_for(op, t);
+          if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cinp, op.epi, kc) > lds_max) continue;
+          c.push_back(t);
+        }
     return c;
+  };
+  auto set_tile = [&](MOp& op, const Tile& t) {
+    op.mt = t.mt; op.ntw = t.ntw; op.rpw = t.rpw;
+    op.kchunk = kchunk_for(op, t);
   };
 
   // zero the level state so that timing runs read finite data
@@ -269,9 +282,18 @@ mcmg_status Ctx::plan_mfma() {
   } cleanup{ev0, ev1};
 
   // choose a tile for op; `launch` runs it once with the chosen tile
+  Tile forced{0, 0, 0};
+  if (const char* ft = getenv("MCMG_FORCE_TILE"))
+    if (sscanf(ft, "%d,%d,%d", &forced.mt, &forced.ntw, &forced.rpw) != 3) forced = Tile{0, 0, 0};
   auto choose = [&](MOp& op, auto&& launch) -> mcmg_status {
     auto cands = candidates(op);
     if (cands.empty()) return MCMG_OK;   // stays on the VALU path
+    for (auto& c : cands)
+      if (c == forced) {
+        set_tile(op, c);
+        op.on = true;
+        return MCMG_OK;
+      }
     const std::string key = tune_key(dim, bf, op);
     {
       std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -279,21 +301,20 @@ mcmg_status Ctx::plan_mfma() {
       auto it = g_tune.find(key);
       if (it != g_tune.end()) {
         for (auto& c : cands)
-          if (c.first == it->second.first && c.second == it->second.second) {
-            op.mt = c.first; op.ntw = c.second; op.on = true;
-            op.kchunk = kchunk_for(op, op.mt, op.ntw);
+          if (c == it->second) {
+            set_tile(op, c);
+            op.on = true;
             return MCMG_OK;
           }
       }
     }
-    op.mt = cands[0].first; op.ntw = cands[0].second; op.on = true;
-    op.kchunk = kchunk_for(op, op.mt, op.ntw);
+    set_tile(op, cands[0]);
+    op.on = true;
     if (!tune || cands.size() == 1) return MCMG_OK;
     float best = 1e30f;
-    std::pair<int, int> bc = cands[0];
+    Tile bc = cands[0];
     for (auto& c : cands) {
-      op.mt = c.first; op.ntw = c.second;
-      op.kchunk = kchunk_for(op, op.mt, op.ntw);
+      set_tile(op, c);
       hipError_t e = launch();                      // warm-up
       if (e != hipSuccess) return fail(MCMG_E_HIP, "tune: %s", hipGetErrorString(e));
       if ((e = hipEventRecord(ev0, stream)) != hipSuccess) return fail(MCMG_E_HIP, "tune event");
@@ -305,8 +326,7 @@ mcmg_status Ctx::plan_mfma() {
       hipEventElapsedTime(&ms, ev0, ev1);
       if (ms < best) { best = ms; bc = c; }
     }
-    op.mt = bc.first; op.ntw = bc.second;
-    op.kchunk = kchunk_for(op, op.mt, op.ntw);
+    set_tile(op, bc);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = bc;
     save_cache_locked();

@@ -19,7 +19,7 @@ mcmg_status fail(mcmg_status s, const char* fmt, ...);
 struct MOp {
   bool on = false;
   int mode = 0, epi = 0, cin = 0, cout = 0, cinp = 0, ncols = 0, npairs = 0, nsteps = 0;
-  int mt = 2, ntw = 1, kchunk = 1;
+  int mt = 2, ntw = 1, rpw = 1, kchunk = 1;
   Dims in{}, out{};
 };
 

@@ -99,6 +99,28 @@ def test_apply_matches_oracle(name):
     assert err <= 1e-5, err
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,tile", [("ragged2d", "1,1,2"), ("ragged2d", "2,2,2"),
+                                       ("bump64", "4,1,2"), ("ragged3d", "1,1,2"),
+                                       ("ragged3d", "2,1,4"), ("chunked3d", "1,1,4"),
+                                       ("chunked3d", "4,2,2")])
+def test_apply_every_tile_shape(name, tile, precision, monkeypatch):
+    """Each matrix-core tile shape (16*mt nodes per wave row, ntw column
+    tiles, rpw rows per wave), forced where it fits, against the oracle."""
+    monkeypatch.setenv("MCMG_FORCE_TILE", tile)
+    dim, n, npml, ch = CASES[name]
+    say(f"[tile] {name} {tile} {precision}")
+    p = problem(dim, n, npml, ch)
+    _, _, M = oracle_parts(p)
+    H = handle(p, precision)
+    r = synth.random_rhs(H.ext_shape, 5)
+    z = to_dev(np.zeros_like(r))
+    H.apply(to_dev(r), z)
+    err = rel_l2(to_host(z), M(r))
+    say(f"  rel L2 {err:.3e}")
+    assert err <= (1e-5 if precision == "fp32" else 2e-2), err
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_apply_bf16_within_budget(name):
     """bf16 matrix-core operands with float32 accumulation and float32 state:
