@@ -52,9 +52,9 @@ def roofline_for(rec, precision):
     under (ridge = peak flops / peak bytes)."""
     fl, by, ms = rec["flops_per_launch"], rec["bytes_per_launch"], rec["avg_ms"]
     name = rec["name"]
-    if name.startswith("mconv_kernel<") and ", true," in name:
+    if name.startswith(("mconv_kernel<", "mstep_kernel<")) and ", true," in name:
         peak_fl, unit_bound = PEAK_BF16_TFLOPS, "mfma"
-    elif name.startswith("mconv_kernel"):
+    elif name.startswith(("mconv_kernel", "mstep_kernel")):
         peak_fl, unit_bound = PEAK_FP32_TFLOPS, "mfma"
     elif name.startswith(("multidot", "update", "zupdate", "helm")):
         peak_fl, unit_bound = PEAK_FP64_TFLOPS, "alu"

@@ -109,8 +109,9 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     return reinterpret_cast<uint4*>(bsm + (((size_t)a * 4 * kchunk + row) * BROW) * ES + (size_t)vv * 16);
   };
   // The first weight chunk is fetched together with the input tile when it
-  // fits in WB vectors per thread: one memory latency for both.
-  constexpr int WB = 4;
+  // fits in WB vectors per thread (40 KB per block): one memory latency for
+  // both instead of one per batch.
+  constexpr int WB = 10;
   const int ks0 = nsteps < kchunk ? nsteps : kchunk;
   const int wtot0 = NACC * 4 * ks0 * V16;
   const bool wpre = wtot0 <= 256 * WB;
@@ -177,6 +178,50 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
+
+  // output offsets and epilogue operands of every accumulator element; for
+  // small tiles the operands are fetched here, so their latency overlaps
+  // the K loop instead of following it
+  constexpr bool PREF = RPW * MT * NTW <= 2;
+  auto out_off = [&](int i, int m, int t, int rr) -> long long {
+    const int rho = wave + 4 * i;
+    const int gy = y0 + rho % G::TY, gz = z0 + rho / G::TY;
+    const int col = col0 + t * 16 + li;
+    const int gx = x0 + m * 16 + 4 * lg + rr;
+    if (MODE == CONV_T2) {
+      // column = class * cout + c; class bits: x fastest
+      const int cls = col / cout, c = col - cls * cout;
+      const int ax = cls & 1, ay = (cls >> 1) & 1, az = (D == 3) ? ((cls >> 2) & 1) : 0;
+      const int fx = 2 * gx + ax, fy = 2 * gy + ay, fz = (D == 3) ? 2 * gz + az : 0;
+      if (cls < (1 << D) && fx < OX && fy < OY && fz < OZ)
+        return (((long long)fz * OY + fy) * OX + fx) * cout + c;
+    } else {
+      if (col < cout && gx < OX && gy < OY && gz < OZ)
+        return (((long long)gz * OY + gy) * OX + gx) * cout + col;
+    }
+    return -1;
+  };
+  float pe0[PREF ? RPW : 1][PREF ? MT : 1][PREF ? NTW : 1][4];
+  float pe1[PREF ? RPW : 1][PREF ? MT : 1][PREF ? NTW : 1][4];
+  if constexpr (PREF && EPI != EPI_SET) {
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t)
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const long long o = out_off(i, m, t, rr);
+            pe0[i][m][t][rr] = 0.f;
+            pe1[i][m][t][rr] = 0.f;
+            if (o >= 0) {
+              if (EPI == EPI_ADD) pe0[i][m][t][rr] = y[o];
+              else if (EPI == EPI_MUL) pe0[i][m][t][rr] = feat[o];
+              else if (EPI == EPI_RESID) { pe0[i][m][t][rr] = r[o]; pe1[i][m][t][rr] = feat[o]; }
+            }
+          }
+  }
 
   floatx4 acc[NACC][RPW][MT][NTW];
 #pragma unroll
@@ -262,42 +307,31 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   }
 
   // ---- epilogue: per (row, m) the operands of all its outputs are loaded
-  // first, then combined and stored
+  // first (unless prefetched), then combined and stored
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
-    const int rho = wave + 4 * i;
-    const int gy = y0 + rho % G::TY, gz = z0 + rho / G::TY;
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
       long long o[NTW][4];
       float e0[NTW][4], e1[NTW][4];
 #pragma unroll
-      for (int t = 0; t < NTW; ++t) {
-        const int col = col0 + t * 16 + li;
+      for (int t = 0; t < NTW; ++t)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const int gx = x0 + m * 16 + 4 * lg + rr;
-          o[t][rr] = -1;
-          if (MODE == CONV_T2) {
-            // column = class * cout + c; class bits: x fastest
-            const int cls = col / cout, c = col - cls * cout;
-            const int ax = cls & 1, ay = (cls >> 1) & 1, az = (D == 3) ? ((cls >> 2) & 1) : 0;
-            const int fx = 2 * gx + ax, fy = 2 * gy + ay, fz = (D == 3) ? 2 * gz + az : 0;
-            if (cls < (1 << D) && fx < OX && fy < OY && fz < OZ)
-              o[t][rr] = (((long long)fz * OY + fy) * OX + fx) * cout + c;
+          o[t][rr] = out_off(i, m, t, rr);
+          if constexpr (PREF) {
+            e0[t][rr] = pe0[PREF ? i : 0][PREF ? m : 0][PREF ? t : 0][rr];
+            e1[t][rr] = pe1[PREF ? i : 0][PREF ? m : 0][PREF ? t : 0][rr];
           } else {
-            if (col < cout && gx < OX && gy < OY && gz < OZ)
-              o[t][rr] = (((long long)gz * OY + gy) * OX + gx) * cout + col;
-          }
-          e0[t][rr] = 0.f;
-          e1[t][rr] = 0.f;
-          if (o[t][rr] >= 0) {
-            if (EPI == EPI_ADD) e0[t][rr] = y[o[t][rr]];
-            else if (EPI == EPI_MUL) e0[t][rr] = feat[o[t][rr]];
-            else if (EPI == EPI_RESID) { e0[t][rr] = r[o[t][rr]]; e1[t][rr] = feat[o[t][rr]]; }
+            e0[t][rr] = 0.f;
+            e1[t][rr] = 0.f;
+            if (o[t][rr] >= 0) {
+              if (EPI == EPI_ADD) e0[t][rr] = y[o[t][rr]];
+              else if (EPI == EPI_MUL) e0[t][rr] = feat[o[t][rr]];
+              else if (EPI == EPI_RESID) { e0[t][rr] = r[o[t][rr]]; e1[t][rr] = feat[o[t][rr]]; }
+            }
           }
         }
-      }
 #pragma unroll
       for (int t = 0; t < NTW; ++t)
 #pragma unroll

@@ -33,8 +33,10 @@ bool differs(const RecOp& a, const RecOp& b) {
              a.conv.feat != b.conv.feat;
     case 1:
       return a.mf.x != b.mf.x || a.mf.y != b.mf.y || a.mf.r != b.mf.r || a.mf.feat != b.mf.feat;
-    default:
+    case 2:
       return a.l1.e != b.l1.e || a.l1.eo != b.l1.eo || a.l1.r != b.l1.r;
+    default:
+      return a.st.e != b.st.e || a.st.eo != b.st.eo || a.st.r != b.st.r || a.st.wSM != b.st.wSM;
   }
 }
 
@@ -64,7 +66,7 @@ mcmg_status Engine::open(const Ctx* c) {
   for (const Level& lv : c->lev) {
     C_.push_back(lv.C); nu1_.push_back(lv.nu1); nu2_.push_back(lv.nu2);
     l1_.push_back(!lv.l1w.empty());
-    mf_.push_back(lv.op_resid.on * 4 + lv.op_R.on * 2 + lv.op_P.on);
+    mf_.push_back(lv.op_resid.on * 4 + lv.op_R.on * 2 + lv.op_P.on + lv.step_on * 8);
   }
   return MCMG_OK;
 }
@@ -78,7 +80,7 @@ bool Engine::compatible(const Ctx* c, std::string* why) const {
     const Level& lv = c->lev[l];
     if (lv.C != C_[l] || lv.nu1 != nu1_[l] || lv.nu2 != nu2_[l]) return no("level structure differs");
     if ((int)!lv.l1w.empty() != l1_[l] ||
-        lv.op_resid.on * 4 + lv.op_R.on * 2 + lv.op_P.on != mf_[l])
+        lv.op_resid.on * 4 + lv.op_R.on * 2 + lv.op_P.on + lv.step_on * 8 != mf_[l])
       return no("kernel plan differs");
     if (lv.nu1 == 0) return no("batched solves need nu1 > 0 on every level");
   }
@@ -176,6 +178,19 @@ mcmg_status Engine::build() {
           a.kchunk = ot.proto.mf.kchunk;
           int nblk;
           tab[(size_t)r * np + i] = mfma_args(a, &nblk);
+          if (r == 0) pre[i + 1] = pre[i] + nblk;
+        }
+      ot.tab_off = b.add(tab);
+    } else if (ot.kind == 3) {
+      std::vector<SArgs> tab((size_t)rows * np);
+      for (int r = 0; r < rows; ++r)
+        for (int i = 0; i < np; ++i) {
+          StepLaunch a = works_[i]->ops[r][q].st;
+          a.tile = ot.proto.st.tile;         // one tile shape for the whole launch
+          a.kc1 = ot.proto.st.kc1;
+          a.kc2 = ot.proto.st.kc2;
+          int nblk;
+          tab[(size_t)r * np + i] = step_args(a, &nblk);
           if (r == 0) pre[i + 1] = pre[i] + nblk;
         }
       ot.tab_off = b.add(tab);
@@ -317,6 +332,7 @@ hipError_t Engine::body(bool all_phases) {
                      ot.jdep ? jpos : nullptr};
       if (ot.kind == 0) ECK(launch_conv_batched(ot.proto.conv, bl, s_));
       else if (ot.kind == 1) ECK(launch_conv_mfma_batched(ot.proto.mf, bl, s_));
+      else if (ot.kind == 3) ECK(launch_step_batched(ot.proto.st, bl, s_));
       else ECK(launch_level1_batched(dim_, ot.proto.l1.var, bl, s_));
     }
     BatchLaunch bl{at(hmv_off_), kb.pre_red, np, total_red_, mask_iter, jpos};

@@ -385,9 +385,92 @@ mcmg_status Ctx::plan_mfma() {
       }
     }
   }
+  // fused smoothing steps (one launch per step instead of three) on the 2D
+  // levels with 16 <= C <= 32, where one block computing t and u with halos
+  // beats three launches at every grid size measured; at C = 8 the halo
+  // recompute and at C = 64 the serial weight streaming make it slower.  The
+  // rule depends on C only, so all handles of a model share one launch
+  // schedule (the tile is autotuned).  MCMG_FUSED_STEP=0 keeps three
+  // launches everywhere, =2 fuses every C >= 8 level.
+  const char* fz = getenv("MCMG_FUSED_STEP");
+  const int fuse = fz ? atoi(fz) : 1;
+  for (int l = 0; fuse && dim == 2 && l < L; ++l) {
+    Level& lv = lev[l];
+    if (lv.C < 8 || !lv.op_resid.on || !lv.op_mul.on || !lv.op_add.on || !lv.op_set.on) continue;
+    if (fuse == 1 && (lv.C < 16 || lv.C > 32)) continue;
+    if (lv.m_sm.empty() || !lv.m_W || !lv.m_KA || !lv.m_KS) continue;
+    const MOp& ro = lv.op_resid;
+    const int nct = ro.ncols / 16;
+    if (nct != 1 && nct != 2 && nct != 4) continue;
+    const size_t brow = (size_t)ro.ncols * KV * (bf ? 2 : 4);
+    std::vector<StepLaunch> cands;
+    for (int tile : {1, 0, 2, 3}) {
+      // chunks: whole tensors when they fit beside the region buffers
+      const size_t regions = mstep_lds_bytes(tile, bf, nct, ro.cinp, 0, 0);
+      if (regions + 8 * brow > lds_max) continue;
+      const size_t wb = lds_max - regions;
+      int kc1 = ro.nsteps, kc2 = ro.nsteps;
+      while (kc1 > 1 && 2 * 4 * (size_t)kc1 * brow > wb) kc1 = (kc1 + 1) / 2;
+      while (kc2 > 1 && 4 * (size_t)kc2 * brow > wb) kc2 = (kc2 + 1) / 2;
+      StepLaunch c{};
+      c.var = L1_STEP; c.bf16 = bf; c.tile = tile; c.kc1 = kc1; c.kc2 = kc2;
+      c.wW = lv.m_W; c.wKA = lv.m_KA; c.wKS = lv.m_KS; c.wSM = lv.m_sm[0];
+      c.C = lv.C; c.cinp = ro.cinp; c.ncols = ro.ncols; c.nsteps = ro.nsteps; c.npairs = ro.npairs;
+      c.n = lv.dims;
+      if (mstep_lds_bytes(tile, bf, nct, ro.cinp, kc1, kc2) <= lds_max) cands.push_back(c);
+    }
+    if (cands.empty()) continue;
+    if (!lv.e_alt) {
+      lv.e_alt = (float*)alloc((size_t)lv.dims.total * lv.C * sizeof(float));
+      if (!lv.e_alt) return fail(MCMG_E_OOM, "level allocation failed");
+      hipError_t e = launch_zero_f32(lv.e_alt, lv.dims.total * lv.C, stream);
+      if (e != hipSuccess) return fail(MCMG_E_HIP, "zero: %s", hipGetErrorString(e));
+    }
+    for (auto& c : cands) { c.e = lv.e; c.eo = lv.e_alt; c.r = lv.r; c.a = lv.a; c.s = lv.s; }
+    char kb[160];
+    snprintf(kb, sizeof(kb), "gfx950|%d|%s|step|%d|%dx%dx%d", dim, bf ? "bf16" : "f32", lv.C,
+             lv.dims.n[0], lv.dims.n[1], lv.dims.n[2]);
+    const std::string key = kb;
+    int pick = -1;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      load_cache_locked();
+      auto it = g_tune.find(key);
+      if (it != g_tune.end())
+        for (size_t k = 0; k < cands.size(); ++k)
+          if (cands[k].tile == it->second.mt) pick = (int)k;
+    }
+    if (pick < 0) {
+      pick = 0;
+      if (tune && cands.size() > 1) {
+        float best = 1e30f;
+        for (size_t k = 0; k < cands.size(); ++k) {
+          hipError_t e = launch_step(cands[k], stream);   // warm-up
+          if (e != hipSuccess) return fail(MCMG_E_HIP, "tune: %s", hipGetErrorString(e));
+          if ((e = hipEventRecord(ev0, stream)) != hipSuccess) return fail(MCMG_E_HIP, "tune event");
+          for (int rep = 0; rep < 3; ++rep)
+            if ((e = launch_step(cands[k], stream)) != hipSuccess) return fail(MCMG_E_HIP, "tune: %s", hipGetErrorString(e));
+          if ((e = hipEventRecord(ev1, stream)) != hipSuccess) return fail(MCMG_E_HIP, "tune event");
+          if ((e = hipEventSynchronize(ev1)) != hipSuccess) return fail(MCMG_E_HIP, "tune sync");
+          float ms = 0.f;
+          hipEventElapsedTime(&ms, ev0, ev1);
+          if (ms < best) { best = ms; pick = (int)k; }
+        }
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = Tile{cands[pick].tile, 0, 0};
+        save_cache_locked();
+      }
+    }
+    lv.step = cands[pick];
+    lv.step_on = true;
+  }
   // timing runs wrote into the work buffers; leave them clean
   for (auto& lv : lev) {
     const long long n = lv.dims.total * lv.C;
+    if (lv.e_alt) {
+      hipError_t e = launch_zero_f32(lv.e_alt, n, stream);
+      if (e != hipSuccess) return fail(MCMG_E_HIP, "zero: %s", hipGetErrorString(e));
+    }
     for (float* p : {lv.e, lv.r, lv.t, lv.u}) {
       hipError_t e = launch_zero_f32(p, n, stream);
       if (e != hipSuccess) return fail(MCMG_E_HIP, "zero: %s", hipGetErrorString(e));

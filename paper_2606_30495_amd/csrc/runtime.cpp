@@ -278,6 +278,29 @@ hipError_t Ctx::vcycle(const void* rin, int tin, void* zout, int tout) {
 hipError_t Ctx::smooth_step(Level& lv, int i, bool first) {
   if (!lv.l1w.empty()) return level1(lv, first ? L1_FIRST : L1_STEP, i);
   hipError_t e;
+  if (lv.step_on) {
+    // one fused launch: e_alt = step(e), then the buffers swap
+    StepLaunch l = lv.step;
+    l.var = first ? L1_FIRST : L1_STEP;
+    l.e = lv.e; l.eo = lv.e_alt; l.r = lv.r; l.a = lv.a; l.s = lv.s;
+    l.wSM = lv.m_sm[i];
+    if (rec) {
+      RecOp r{};
+      r.kind = 3;
+      r.st = l;
+      rec->push_back(r);
+      e = hipSuccess;
+    } else if (!prof.on) {
+      e = launch_step(l, stream);
+    } else {
+      const double P = (double)lv.dims.total, C = lv.C;
+      const double fl = 2.0 * 9.0 * C * C * P * (first ? 2.0 : 4.0);
+      const double by = 4.0 * P * C * (first ? 3.0 : 5.0);
+      e = timed(step_kernel_name(l), fl, by, [=] { return launch_step(l, stream); });
+    }
+    if (e == hipSuccess) std::swap(lv.e, lv.e_alt);
+    return e;
+  }
   const float* tin = lv.r;
   if (!first) {
     e = conv_level(lv, EPI_RESID, lv.e, lv.w_W, lv.m_W, lv.w_KA, lv.m_KA, lv.t, lv.r, lv.a);

@@ -10,6 +10,7 @@
 #include "conv_mfma.h"
 #include "internal.h"
 #include "mcmg.h"
+#include "step_mfma.h"
 
 namespace mcmg {
 
@@ -39,6 +40,10 @@ struct Level {
   MOp op_P;                                // prolongation next level -> this
   void *m_W = nullptr, *m_KA = nullptr, *m_KS = nullptr, *m_R = nullptr, *m_P = nullptr;
   std::vector<void*> m_sm;
+  // fused matrix-core smoothing step (2D, C >= 8): tile plan; e ping-pongs
+  // with e_alt
+  StepLaunch step{};
+  bool step_on = false;
   // fused C = 2 sweep: per smoothing step weights; e ping-pongs with e_alt
   std::vector<L1Weights> l1w;
   std::vector<L1Weights*> l1w_dev;          // device copies (batched launches)
@@ -77,10 +82,12 @@ struct Prof {
 // A recorded launch of the V-cycle (record mode): the batched driver replays
 // op i of every problem as one batched launch.
 struct RecOp {
-  int kind;                   // 0 VALU direct conv, 1 matrix-core conv, 2 fused C = 2 sweep
+  int kind;                   // 0 VALU direct conv, 1 matrix-core conv, 2 fused C = 2 sweep,
+                              // 3 fused matrix-core smoothing step
   ConvLaunch conv;
   MfmaConv mf;
   L1Launch l1;
+  StepLaunch st;
   const L1Weights* l1w_dev;   // device copy of the sweep's weights
 };
 

@@ -1,0 +1,300 @@
+// Kernel templates of the fused matrix-core smoothing step (2D, C >= 8; see
+// step_mfma.hip).  Included by the instantiation units step_mfma_i*.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "internal.h"
+#include "step_mfma.h"
+
+namespace mcmg {
+
+namespace {
+
+typedef float sfloatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 sbf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short sf2bf(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+
+// Output tile TX x TY per tile id; regions grow by one node per side per
+// phase: R3 = tile, R2 = tile + 1 (u), R1 = tile + 2 (t), R0 = tile + 3 (e).
+template <int TI> struct STile;
+template <> struct STile<0> { static constexpr int TX = 16, TY = 4; };
+template <> struct STile<1> { static constexpr int TX = 32, TY = 4; };
+template <> struct STile<2> { static constexpr int TX = 32, TY = 8; };
+template <> struct STile<3> { static constexpr int TX = 64, TY = 8; };
+
+template <int TI, bool BF, int NCT>
+struct SGeo {
+  static constexpr int TX = STile<TI>::TX, TY = STile<TI>::TY;
+  static constexpr int W0 = TX + 6, H0 = TY + 6, N0 = W0 * H0;
+  static constexpr int W1 = TX + 4, H1 = TY + 4, N1 = W1 * H1;
+  static constexpr int W2 = TX + 2, H2 = TY + 2, N2 = W2 * H2;
+  static constexpr int N3 = TX * TY;
+  static constexpr int KV = BF ? 8 : 1, ES = BF ? 2 : 4;
+  static constexpr int NCOL = 16 * NCT;
+};
+
+// One phase: for the region's row tiles (16 consecutive region nodes each,
+// split over the 4 waves in groups of GR), acc[a] = sum over K of
+// A(src region, tap offsets) x B(weights of tensor a); then `epi` stores
+// the results.  Weights stream through LDS in chunks of `kc` K-steps.
+template <bool BF, int NCT, int NACC, int GR, class Epi>
+__device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src, int srcW, int dstW,
+                                       int ndst, const void* w0, const void* w1,
+                                       unsigned char* wbuf, int kc, Epi epi) {
+  constexpr int KV = BF ? 8 : 1, ES = BF ? 2 : 4;
+  constexpr int BROW = NCT * 16 * KV;           // elements of one pair row of the weights
+  constexpr int V16 = BROW * ES / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int stride = A.cinp + (BF ? 8 : 1);
+  const int cpv = A.cinp / KV;
+  const int nsteps = A.nsteps, npairs = A.npairs, ncols = A.ncols;
+  const int ntile = (ndst + 15) / 16;
+  const int per_wave = (ntile + 3) / 4;
+  const int ngroups = (per_wave + GR - 1) / GR;
+  const bool resident = kc >= nsteps;            // all weights of the phase fit at once
+  for (int g = 0; g < ngroups; ++g) {
+    sfloatx4 acc[NACC][GR][NCT];
+#pragma unroll
+    for (int a = 0; a < NACC; ++a)
+#pragma unroll
+      for (int i = 0; i < GR; ++i)
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[a][i][t] = sfloatx4{0.f, 0.f, 0.f, 0.f};
+    // source node of each of this lane's row tiles (A row li)
+    int snode[GR];
+    bool live[GR];
+#pragma unroll
+    for (int i = 0; i < GR; ++i) {
+      const int tile = wave + 4 * (g * GR + i);
+      live[i] = tile < ntile;
+      int n = tile * 16 + li;
+      if (n >= ndst) n = ndst - 1;
+      if (n < 0) n = 0;
+      const int hy = n / dstW, hx = n - hy * dstW;
+      snode[i] = hy * srcW + hx;                 // tap (0, 0) of the halo-1 source
+    }
+    for (int s0 = 0; s0 < nsteps; s0 += kc) {
+      const int ks = (nsteps - s0) < kc ? (nsteps - s0) : kc;
+      if (!resident || (g == 0 && s0 == 0)) {
+        __syncthreads();                         // previous chunk consumed
+        const int total = NACC * 4 * ks * V16;
+        for (int idx = threadIdx.x; idx < total; idx += 256) {
+          const int a = idx / (4 * ks * V16), rem = idx % (4 * ks * V16);
+          const int row = rem / V16, vv = rem % V16;
+          const uint4 v = *reinterpret_cast<const uint4*>(
+              reinterpret_cast<const unsigned char*>(a ? w1 : w0) +
+              ((size_t)(4 * s0 + row) * ncols * KV) * ES + (size_t)vv * 16);
+          *reinterpret_cast<uint4*>(wbuf + (((size_t)a * 4 * kc + row) * BROW) * ES + (size_t)vv * 16) = v;
+        }
+        __syncthreads();
+      }
+      for (int ss = 0; ss < ks; ++ss) {
+        const int s = s0 + ss;
+        int q = 4 * s + lg;
+        if (q >= npairs) q = npairs - 1;         // weight rows are zero there
+        const int tap = q / cpv, cb = q - tap * cpv;
+        const int toff = (tap / 3) * srcW + (tap % 3);
+        const int wrow = resident ? s : ss;
+        typename std::conditional<BF, sbf16x8, float>::type bfr[NACC][NCT];
+#pragma unroll
+        for (int a = 0; a < NACC; ++a)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) {
+            const size_t o = ((size_t)a * 4 * kc + 4 * wrow + lg) * BROW + (t * 16 + li) * KV;
+            if constexpr (BF) bfr[a][t] = *reinterpret_cast<const sbf16x8*>(reinterpret_cast<const unsigned short*>(wbuf) + o);
+            else bfr[a][t] = reinterpret_cast<const float*>(wbuf)[o];
+          }
+#pragma unroll
+        for (int i = 0; i < GR; ++i) {
+          if (!live[i]) continue;
+          const size_t node = (size_t)(snode[i] + toff);
+          if constexpr (BF) {
+            const sbf16x8 af = *reinterpret_cast<const sbf16x8*>(
+                reinterpret_cast<const unsigned short*>(src) + node * stride + cb * KV);
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+              for (int a = 0; a < NACC; ++a)
+                acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[a][t], acc[a][i][t], 0, 0, 0);
+          } else {
+            const float af = reinterpret_cast<const float*>(src)[node * stride + cb];
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+#pragma unroll
+              for (int a = 0; a < NACC; ++a)
+                acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bfr[a][t], acc[a][i][t], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // results: lane (li, lg) holds rows 4 lg + rr of each tile, column li
+#pragma unroll
+    for (int i = 0; i < GR; ++i) {
+      if (!live[i]) continue;
+      const int tile = wave + 4 * (g * GR + i);
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int n = tile * 16 + 4 * lg + rr;
+          if (n < ndst) epi(n, t * 16 + li, acc[0][i][t][rr], acc[NACC - 1][i][t][rr]);
+        }
+    }
+  }
+}
+
+// The fused step e' = e + Wsm * (s (.) (KS * (r - W*e - a (.) (KA*e)))) on one
+// output tile; FIRST (e = 0): e' = Wsm * (s (.) (KS * r)).
+template <int TI, bool BF, int NCT, int VAR>
+__device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
+  using G = SGeo<TI, BF, NCT>;
+  constexpr int ES = G::ES;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int C = A.C, cinp = A.cinp;
+  const int stride = cinp + (BF ? 8 : 1);
+  const int NY = A.n.n[0], NX = A.n.n[1];
+  const int ntiles = A.tiles_x * A.tiles_y;
+  const int per = (ntiles + 7) / 8;
+  const int tl = (vblk % 8) * per + vblk / 8;   // XCD-contiguous bands
+  if (tl >= ntiles) return;
+  const int x0 = (tl % A.tiles_x) * G::TX, y0 = (tl / A.tiles_x) * G::TY;
+  // LDS: region buffers (R0 and R2 share storage: e is dead once t exists),
+  // then the weight chunk buffer
+  auto rbytes = [&](int n) { return (((size_t)n * stride * ES + 15) / 16) * 16; };
+  unsigned char* b02 = smem;
+  unsigned char* b1 = smem + (rbytes(G::N0) > rbytes(G::N2) ? rbytes(G::N0) : rbytes(G::N2));
+  unsigned char* wbuf = b1 + rbytes(G::N1);
+  auto inside = [&](int y, int x) { return x >= 0 && x < NX && y >= 0 && y < NY; };
+  auto put = [&](unsigned char* buf, int node, int c, float v) {
+    if constexpr (BF) reinterpret_cast<unsigned short*>(buf)[(size_t)node * stride + c] = sf2bf(v);
+    else reinterpret_cast<float*>(buf)[(size_t)node * stride + c] = v;
+  };
+  // stage a FP32 field [nodes][C] on a region of width W, height H, halo h
+  auto stage = [&](unsigned char* buf, const float* __restrict__ f, int W, int H, int h) {
+    const int ng = cinp / 4;
+    const int total = W * H * ng;
+    const bool vec4 = (C % 4) == 0;
+    for (int idx = threadIdx.x; idx < total; idx += 256) {
+      const int node = idx / ng, c = (idx % ng) * 4;
+      const int hy = node / W, hx = node - hy * W;
+      const int gy = y0 - h + hy, gx = x0 - h + hx;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (inside(gy, gx) && c < C) {
+        const float* p = f + ((size_t)gy * NX + gx) * C + c;
+        if (vec4) v = *reinterpret_cast<const float4*>(p);
+        else {
+          v.x = p[0];
+          if (c + 1 < C) v.y = p[1];
+          if (c + 2 < C) v.z = p[2];
+          if (c + 3 < C) v.w = p[3];
+        }
+      }
+      put(buf, node, c, v.x); put(buf, node, c + 1, v.y); put(buf, node, c + 2, v.z); put(buf, node, c + 3, v.w);
+    }
+  };
+  constexpr int GR1 = (8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1;
+  constexpr int GR2 = (8 / NCT) > 0 ? 8 / NCT : 1;
+
+  // ---- phase 1: t on R1 (FIRST: t = r)
+  if (VAR == L1_FIRST) {
+    stage(b1, A.r, G::W1, G::H1, 2);
+  } else {
+    stage(b02, A.e, G::W0, G::H0, 3);
+    // (the chunk loop's first barrier orders the staging before any read)
+    sphase<BF, NCT, 2, GR1>(A, b02, G::W0, G::W1, G::N1, A.wW, A.wKA, wbuf, A.kc1,
+        [&](int n, int c, float aw, float aka) {
+          if (c >= cinp) return;
+          const int hy = n / G::W1, hx = n - hy * G::W1;
+          const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
+          float v = 0.f;
+          if (c < C && inside(gy, gx)) {
+            const size_t o = ((size_t)gy * NX + gx) * C + c;
+            v = A.r[o] - aw - A.a[o] * aka;
+          }
+          put(b1, n, c, v);
+        });
+  }
+  __syncthreads();
+  // ---- phase 2: u = s (.) (KS * t) on R2 (into the R0 storage)
+  sphase<BF, NCT, 1, GR2>(A, b1, G::W1, G::W2, G::N2, A.wKS, nullptr, wbuf, A.kc2,
+      [&](int n, int c, float acc, float) {
+        if (c >= cinp) return;
+        const int hy = n / G::W2, hx = n - hy * G::W2;
+        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        float v = 0.f;
+        if (c < C && inside(gy, gx)) v = A.s[((size_t)gy * NX + gx) * C + c] * acc;
+        put(b02, n, c, v);
+      });
+  __syncthreads();
+  // ---- phase 3: e' = e + Wsm * u on the tile
+  sphase<BF, NCT, 1, GR2>(A, b02, G::W2, G::TX, G::N3, A.wSM, nullptr, wbuf, A.kc2,
+      [&](int n, int c, float acc, float) {
+        const int hy = n / G::TX, hx = n - hy * G::TX;
+        const int gy = y0 + hy, gx = x0 + hx;
+        if (c >= C || !inside(gy, gx)) return;
+        const size_t o = ((size_t)gy * NX + gx) * C + c;
+        A.eo[o] = (VAR == L1_FIRST) ? acc : A.e[o] + acc;
+      });
+}
+
+template <int TI, bool BF, int NCT, int VAR>
+__global__ __launch_bounds__(256) void mstep_kernel(SArgs A) {
+  mstep_body<TI, BF, NCT, VAR>(A, blockIdx.x);
+}
+
+template <int TI, bool BF, int NCT, int VAR>
+__global__ __launch_bounds__(256) void mstep_kernel_batched(const SArgs* __restrict__ tab,
+                                                            const int* __restrict__ pre, int np,
+                                                            const int* __restrict__ frozen,
+                                                            const int* __restrict__ row) {
+  const int p = batch_find(pre, np, blockIdx.x);
+  if (frozen && frozen[p]) return;
+  const SArgs A = tab[batch_entry(row, np, p)];
+  mstep_body<TI, BF, NCT, VAR>(A, blockIdx.x - pre[p]);
+}
+
+template <int TI, bool BF, int NCT, int VAR>
+hipError_t srun(const StepLaunch& l, const BatchLaunch* b, hipStream_t s) {
+  const size_t lds = mstep_lds_bytes(l.tile, l.bf16, l.ncols / 16, l.cinp, l.kc1, l.kc2);
+  if (b) {
+    hipLaunchKernelGGL((mstep_kernel_batched<TI, BF, NCT, VAR>), dim3(b->total), dim3(256), lds, s,
+                       (const SArgs*)b->tab, b->pre, b->np, b->frozen, b->row);
+  } else {
+    int nblk;
+    const SArgs A = step_args(l, &nblk);
+    hipLaunchKernelGGL((mstep_kernel<TI, BF, NCT, VAR>), dim3(nblk), dim3(256), lds, s, A);
+  }
+  return hipGetLastError();
+}
+
+template <bool BF>
+hipError_t sdispatch(const StepLaunch& l, const BatchLaunch* b, hipStream_t s) {
+#define SCASE(TI, NCT)                                                                   \
+  if (l.tile == TI && l.ncols == 16 * NCT)                                               \
+    return l.var == L1_FIRST ? srun<TI, BF, NCT, L1_FIRST>(l, b, s) : srun<TI, BF, NCT, L1_STEP>(l, b, s);
+  SCASE(0, 1) SCASE(0, 2) SCASE(0, 4)
+  SCASE(1, 1) SCASE(1, 2) SCASE(1, 4)
+  SCASE(2, 1) SCASE(2, 2) SCASE(2, 4)
+  SCASE(3, 1) SCASE(3, 2) SCASE(3, 4)
+#undef SCASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+}  // namespace mcmg
+
+#define MSTEP_UNIT(NAME, BF)                                                              \
+  namespace mcmg {                                                                         \
+  hipError_t NAME(const StepLaunch& l, const BatchLaunch* b, hipStream_t s) {             \
+    return sdispatch<BF>(l, b, s);                                                         \
+  }                                                                                        \
+  }

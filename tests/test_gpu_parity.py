@@ -121,6 +121,26 @@ def test_apply_every_tile_shape(name, tile, precision, monkeypatch):
     assert err <= (1e-5 if precision == "fp32" else 2e-2), err
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("name", ["bump64", "ragged2d"])
+def test_fused_step_bitwise_equals_three_launches(name, precision, monkeypatch):
+    """The fused matrix-core smoothing step rounds t and u where the three
+    separate convolutions do and sums K in the same order: same bits."""
+    dim, n, npml, ch = CASES[name]
+    say(f"[fused-step] {name} {precision}")
+    p = problem(dim, n, npml, ch)
+    r = synth.random_rhs((n + 2 * npml,) * dim, 9)
+    out = []
+    for fused in ("1", "0"):
+        monkeypatch.setenv("MCMG_FUSED_STEP", fused)
+        H = handle(p, precision)
+        z = to_dev(np.zeros_like(r))
+        H.apply(to_dev(r), z)
+        out.append(to_host(z))
+        H.close()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_apply_bf16_within_budget(name):
     """bf16 matrix-core operands with float32 accumulation and float32 state:
