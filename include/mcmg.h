@@ -52,10 +52,18 @@ typedef enum { MCMG_FP32 = 0, MCMG_BF16 = 1 } mcmg_precision;
 
 typedef struct { int dim; int n[3]; } mcmg_grid;           /* interior nodes */
 
-/* PML: ncells per side; sigma_max <= 0 selects the default
- * 3 ln(1e6) / (2 (omega / max c) ncells h) (round-trip factor 1e-6).
- * Stretch s = 1 + i sigma_max (d / ncells)^2, d = cells into the layer. */
-typedef struct { int ncells; double sigma_max; } mcmg_pml;
+/* Absorbing layer of ncells cells on every side of the interior grid.
+ * kind MCMG_ABL_PML (App. A.1.1): complex stretching s = 1 + i sigma,
+ *   sigma = sigma_max (d / ncells)^2 (d = cells into the layer), operator in
+ *   divergence form; sigma_max <= 0 selects 3 ln(1e6) / (2 (omega / max c)
+ *   ncells h) (round-trip factor 1e-6).
+ * kind MCMG_ABL_SPONGE (Sec. 2.1): -Lap u - k^2 (1 + i gamma) u with
+ *   gamma = sigma_max min(1, sum_a (d_a / ncells)^2) (d_a = cells into the
+ *   layer along axis a); sigma_max <= 0 selects 3 ln(1e6) / ((omega / max c)
+ *   ncells h).  The damping sign is the one that absorbs waves leaving the
+ *   domain under the radiation condition of Eq. helm (outgoing e^{+ikr}). */
+enum { MCMG_ABL_PML = 0, MCMG_ABL_SPONGE = 1 };
+typedef struct { int ncells; double sigma_max; int kind; } mcmg_pml;
 
 /* Self-describing weight blob (host memory; copied by mcmg_setup).
  * Header: magic "MCMGWB01", version 1, dim, levels L <= 8, ksize 3,

@@ -31,7 +31,10 @@ class Grid(ctypes.Structure):
 
 
 class Pml(ctypes.Structure):
-    _fields_ = [("ncells", ctypes.c_int), ("sigma_max", ctypes.c_double)]
+    _fields_ = [("ncells", ctypes.c_int), ("sigma_max", ctypes.c_double), ("kind", ctypes.c_int)]
+
+
+ABSORBER = {"pml": 0, "sponge": 1}
 
 
 class Weights(ctypes.Structure):
@@ -160,7 +163,7 @@ class Handle:
     """One medium: setup once (Alg. 1), then apply / matvec / solve."""
 
     def __init__(self, c, omega, h, npml, blob, precision="fp32", restart=30, sigma_max=0.0,
-                 stream=None, ortho=0):
+                 stream=None, ortho=0, absorber="pml"):
         c = np.ascontiguousarray(c, dtype=np.float64)
         g = Grid(c.ndim, (ctypes.c_int * 3)(*(list(c.shape) + [1] * (3 - c.ndim))))
         self._blob = bytes(blob)
@@ -168,8 +171,8 @@ class Handle:
         opts = Opts(PRECISION[precision], int(restart), _stream_ptr(stream), int(ortho))
         out = ctypes.c_void_p()
         _check(lib().mcmg_setup(c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), g, float(omega),
-                                float(h), Pml(int(npml), float(sigma_max)), w, ctypes.byref(opts),
-                                ctypes.byref(out)))
+                                float(h), Pml(int(npml), float(sigma_max), ABSORBER[absorber]), w,
+                                ctypes.byref(opts), ctypes.byref(out)))
         self.ptr = out
         d = ctypes.c_int()
         ne = (ctypes.c_int * 3)()
@@ -298,7 +301,7 @@ class Server:
         return mid.value
 
     def add_medium(self, c, omega, h, npml, blob, precision="bf16", restart=30, sigma_max=0.0,
-                   ortho=0):
+                   ortho=0, absorber="pml"):
         c = np.ascontiguousarray(c, dtype=np.float64)
         g = Grid(c.ndim, (ctypes.c_int * 3)(*(list(c.shape) + [1] * (3 - c.ndim))))
         b = bytes(blob)
@@ -306,7 +309,8 @@ class Server:
         opts = Opts(PRECISION[precision], int(restart), None, int(ortho))
         mid = ctypes.c_int()
         _check(lib().mcmg_server_add_medium(self.ptr, c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                            g, float(omega), float(h), Pml(int(npml), float(sigma_max)),
+                                            g, float(omega), float(h),
+                                            Pml(int(npml), float(sigma_max), ABSORBER[absorber]),
                                             w, ctypes.byref(opts), ctypes.byref(mid)))
         self._shapes.append(tuple(s + 2 * int(npml) for s in c.shape))
         return mid.value

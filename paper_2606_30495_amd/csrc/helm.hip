@@ -1,10 +1,13 @@
-// Helmholtz + PML operator in FP64 (Sec. 2.1 Eq. FDM_stencil, App. A.1.1)
-// and the setup kernels that build its coefficients.
+// Helmholtz operator with an absorbing layer in FP64 (Sec. 2.1 Eq.
+// FDM_stencil and the sponge equation, App. A.1.1 PML) and the setup kernels
+// that build its coefficients.
 //
-// (A u)_I = sum_a [ (cm_a + cp_a) u_I - cm_a u_{I-e_a} - cp_a u_{I+e_a} ] - k_I^2 u_I
+// (A u)_I = sum_a [ (cm_a + cp_a) u_I - cm_a u_{I-e_a} - cp_a u_{I+e_a} ]
+//           - k_I^2 (1 + i gamma_I) u_I
 // with cm_a = 1/(h^2 s_a(I) s_a(I-1/2)), cp_a = 1/(h^2 s_a(I) s_a(I+1/2))
 // (divergence form of the stretched Laplacian; Dirichlet zero outside the
-// extended grid).  Per node it streams u (16 B), k^2 (8 B) and the output
+// extended grid).  PML: gamma = 0; sponge: s = 1 and gamma = gmax min(1,
+// sum_a g_a[I_a]) from per-axis tables.  Per node it streams u (16 B), k^2 (8 B) and the output
 // (16 B); the residual form also reads f (16 B) and emits block partial sums
 // of |f - A u|^2 for the FP64 norm.
 #include "internal.h"
@@ -68,6 +71,15 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
     const cplx uc = ld(u, p);
     const double kk = k2[p];
     cplx acc = {-kk * uc.re, -kk * uc.im};
+    if (A.op.gmax != 0.0) {
+      double gs = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) gs += A.op.g[a][i[a]];
+      const double gk = kk * A.op.gmax * (gs < 1.0 ? gs : 1.0);
+      // -k^2 (1 + i gamma) u: the damping part is -i k^2 gamma u
+      acc.re += gk * uc.im;
+      acc.im -= gk * uc.re;
+    }
     const long long stride[3] = {(long long)n.n[1] * n.n[2], (long long)n.n[2], 1};
     const double* cms[3] = {cm0, cm1, cm2};
     const double* cps[3] = {cp0, cp1, cp2};

@@ -79,6 +79,9 @@ struct HelmOp {
   const double* k2;       // [nodes]
   const double* cm[3];    // complex [n_a] (interleaved)
   const double* cp[3];
+  // sponge layer: diagonal -k^2 (1 + i gamma), gamma = gmax min(1, sum_a g_a[i_a])
+  double gmax;            // 0: no sponge term
+  const double* g[3];     // [n_a] squared normalised distance into the layer
 };
 
 // out = A u (f == nullptr) or out = f - A u; if partial != nullptr the

@@ -426,7 +426,8 @@ HelmOp Ctx::helm() const {
   op.dim = dim;
   op.ext = ext;
   op.k2 = k2;
-  for (int a = 0; a < 3; ++a) { op.cm[a] = cm[a]; op.cp[a] = cp[a]; }
+  for (int a = 0; a < 3; ++a) { op.cm[a] = cm[a]; op.cp[a] = cp[a]; op.g[a] = gtab[a]; }
+  op.gmax = absorber == MCMG_ABL_SPONGE ? gamma_max : 0.0;
   return op;
 }
 
@@ -473,10 +474,19 @@ mcmg_status do_setup(const double* c, mcmg_grid grid, double omega, double h, mc
     if (!(c[i] > 0)) return fail(MCMG_E_ARG, "wave speed must be > 0");
     if (c[i] > cmax) cmax = c[i];
   }
-  ctx->sigma_max = pml.sigma_max;
-  if (!(pml.sigma_max > 0)) {
-    ctx->sigma_max = pml.ncells == 0 ? 0.0
-                                     : 3.0 * std::log(1e6) / (2.0 * (omega / cmax) * pml.ncells * h);
+  if (pml.kind != MCMG_ABL_PML && pml.kind != MCMG_ABL_SPONGE)
+    return fail(MCMG_E_ARG, "unknown absorbing layer kind %d", pml.kind);
+  ctx->absorber = pml.kind;
+  const double kref = omega / cmax;
+  if (pml.kind == MCMG_ABL_PML) {
+    ctx->sigma_max = pml.sigma_max;
+    if (!(pml.sigma_max > 0))
+      ctx->sigma_max = pml.ncells == 0 ? 0.0 : 3.0 * std::log(1e6) / (2.0 * kref * pml.ncells * h);
+  } else {
+    ctx->sigma_max = 0.0;              // no stretching
+    ctx->gamma_max = pml.sigma_max;
+    if (!(pml.sigma_max > 0))
+      ctx->gamma_max = pml.ncells == 0 ? 0.0 : 3.0 * std::log(1e6) / (kref * pml.ncells * h);
   }
   mcmg_status st = ctx->parse_weights(w.blob, w.bytes);
   if (st != MCMG_OK) return st;
@@ -518,6 +528,21 @@ mcmg_status do_setup(const double* c, mcmg_grid grid, double omega, double h, mc
   for (int a = 0; a < ctx->dim; ++a) {
     e = launch_pml_tables(ctx->next[a], ctx->npml, h, ctx->sigma_max, ctx->cm[a], ctx->cp[a], s);
     if (e != hipSuccess) return fail(MCMG_E_HIP, "pml tables: %s", hipGetErrorString(e));
+  }
+  if (ctx->absorber == MCMG_ABL_SPONGE) {
+    // per-axis (d_a / npml)^2, d_a = cells into the layer along axis a
+    for (int a = 0; a < ctx->dim; ++a) {
+      std::vector<double> g(ctx->next[a], 0.0);
+      for (int i = 0; i < ctx->next[a] && ctx->npml > 0; ++i) {
+        const int lo = ctx->npml, hi = ctx->npml + ctx->nint[a] - 1;
+        const double dd = i < lo ? lo - i : (i > hi ? i - hi : 0);
+        g[i] = (dd / ctx->npml) * (dd / ctx->npml);
+      }
+      ctx->gtab[a] = (double*)ctx->alloc(g.size() * sizeof(double));
+      if (!ctx->gtab[a]) return fail(MCMG_E_OOM, "setup allocation failed");
+      e = hipMemcpy(ctx->gtab[a], g.data(), g.size() * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return fail(MCMG_E_HIP, "sponge tables: %s", hipGetErrorString(e));
+    }
   }
   e = ctx->run_setup();
   if (e != hipSuccess) return fail(MCMG_E_HIP, "setup convolutions: %s", hipGetErrorString(e));

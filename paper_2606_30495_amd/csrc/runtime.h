@@ -114,6 +114,9 @@ struct Ctx {
   int npml = 0;
   Dims interior{}, ext{};
   double omega = 0, h = 0, sigma_max = 0;
+  int absorber = MCMG_ABL_PML;
+  double gamma_max = 0;                 // sponge damping (absorber == MCMG_ABL_SPONGE)
+  double* gtab[3] = {nullptr, nullptr, nullptr};
   int precision = MCMG_FP32, restart = 30, ortho = 0;
   hipStream_t stream = nullptr;
 

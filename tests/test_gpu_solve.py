@@ -12,7 +12,7 @@ from oracle import helmholtz, krylov, mcmg
 pytestmark = pytest.mark.gpu
 
 
-def classical_problem(n=64, npml=8, channels=(2, 8, 16), ppw=10.0, src=(0.5, 0.25)):
+def classical_problem(n=64, npml=8, channels=(2, 8, 16), ppw=10.0, src=(0.5, 0.25), absorber="pml"):
     L = len(channels)
     nu = (2,) * L
     c = synth.medium_bump(n, 2)
@@ -21,20 +21,22 @@ def classical_problem(n=64, npml=8, channels=(2, 8, 16), ppw=10.0, src=(0.5, 0.2
     tens, feats = synth.shifted_laplacian(c, omega, h, npml, channels, nu, nu)
     f = synth.point_source(n, npml, src, 2)
     return {"n": n, "npml": npml, "channels": channels, "nu": nu, "c": c, "h": h, "omega": omega,
-            "tens": tens, "feats": feats, "f": f,
+            "tens": tens, "feats": feats, "f": f, "absorber": absorber,
             "blob": synth.pack_blob(2, channels, nu, nu, tens)}
 
 
 def gpu_handle(p, precision="fp32", restart=30):
     from paper_2606_30495_amd import Handle
-    H = Handle(p["c"], p["omega"], p["h"], p["npml"], p["blob"], precision=precision, restart=restart)
+    H = Handle(p["c"], p["omega"], p["h"], p["npml"], p["blob"], precision=precision, restart=restart,
+               absorber=p.get("absorber", "pml"))
     for l, (a, s) in enumerate(p["feats"], start=1):
         H.set_features(l, to_dev(a), to_dev(s))
     return H
 
 
 def oracle_solve(p, maxit=500, tol=1e-6):
-    op = helmholtz.setup_operator(p["c"], p["omega"], p["h"], p["npml"])
+    op = helmholtz.setup_operator(p["c"], p["omega"], p["h"], p["npml"],
+                                  absorber=p.get("absorber", "pml"))
     W = mcmg.Weights(2, p["channels"], p["nu"], p["nu"], p["tens"])
     feats = {"a": [None] + [np.moveaxis(a, -1, 0).astype(np.float64) for a, _ in p["feats"]],
              "s": [None] + [np.moveaxis(s, -1, 0).astype(np.float64) for _, s in p["feats"]]}
@@ -96,3 +98,25 @@ def test_warm_restart_and_maxit():
     i2 = H.solve(f, u, tol=1e-6, maxit=500)
     assert i2["converged"] and i2["relres_true"] <= 1e-6
     assert i2["relres_true"] < i1["relres_true"]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_sponge_layer_solve_matches_oracle(precision):
+    """Sponge absorbing layer (Sec. 2.1, -k^2 (1 + i gamma)): the GPU solve
+    reaches FP64 true residual 1e-6 with the oracle's iteration count (FP32
+    within +/-1, BF16 within 1.25x + 2) and the same solution."""
+    say(f"[sponge-solve] {precision}")
+    p = classical_problem(absorber="sponge")
+    uo, io = _oracle_cached("bump64-sponge", p)
+    assert io["converged"]
+    H = gpu_handle(p, precision)
+    u = to_dev(np.zeros_like(p["f"]))
+    info = H.solve(to_dev(p["f"]), u, tol=1e-6, maxit=500)
+    say(f"  gpu {info['iters']} it (oracle {io['iters']}), relres {info['relres_true']:.2e}")
+    assert info["converged"] and info["relres_true"] <= 1e-6
+    if precision == "fp32":
+        assert abs(info["iters"] - io["iters"]) <= 1
+    else:
+        assert info["iters"] <= 1.25 * io["iters"] + 2
+    # both are 1e-6-residual solutions of the same system
+    assert rel_l2(to_host(u), uo) < 1e-3

@@ -134,3 +134,67 @@ def test_outgoing_greens_function():
     err = _greens_error(+1)
     assert err < 0.05, err
     assert _greens_error(-1) > 0.3
+
+
+def _sponge_1d(npml, flip=False):
+    import scipy.sparse.linalg as spl
+    n = 400
+    h = 1.0 / n
+    kh = 2 * math.pi / 20
+    op = helmholtz.setup_operator(np.ones(n), kh / h, h, npml, absorber="sponge")
+    if flip:                                   # the sign as printed: (1 - gamma i)
+        op = dict(op)
+        op["gamma"] = -op["gamma"]
+    j0 = npml + n // 2
+    f = np.zeros(n + 2 * npml, dtype=complex)
+    f[j0] = 1.0
+    u = spl.spsolve(helmholtz.assemble(op).tocsc(), f)
+    # exact outgoing solution of the discrete free-space problem:
+    # u_j = A e^{i xi h |j - j0|}, cos(xi h) = 1 - (k h)^2 / 2, A = i h^2 / (2 sin xi h)
+    xh = math.acos(1 - kh * kh / 2)
+    j = np.arange(n + 2 * npml)
+    ex = 1j * h * h / (2 * math.sin(xh)) * np.exp(1j * xh * np.abs(j - j0))
+    inner = slice(npml, npml + n)
+    err = np.linalg.norm(u[inner] - ex[inner]) / np.linalg.norm(ex[inner])
+    return u, err
+
+
+def test_sponge_absorbs_outgoing_waves_in_1d():
+    """Sponge layer (Sec. 2.1) with k^2 (1 + i gamma): the interior solution of
+    a point source is the discrete outgoing (e^{+ikr}) Green's function up to
+    the layer's small reflection, and the field decays through the layer.
+    The printed factor (1 - gamma i) yields the incoming solution instead
+    (the sign reading this pins)."""
+    u, err = _sponge_1d(60)
+    assert err < 3e-3, err
+    assert abs(u[1]) < 1e-2 * abs(u[60])
+    _, err_flip = _sponge_1d(60, flip=True)
+    assert err_flip > 1.0, err_flip
+    # a longer layer reflects less
+    _, err_long = _sponge_1d(100)
+    assert err_long < err
+
+
+def test_sponge_profile_and_symmetry():
+    """gamma vanishes in the physical domain, grows quadratically with the
+    distance into the layer, saturates at gamma_max; without stretching the
+    operator is complex symmetric (A = A^T) and npml = 0 is the paper's
+    stencil."""
+    n, npml = 12, 4
+    c = np.ones((n, n))
+    op = helmholtz.setup_operator(c, 10.0, 1.0 / n, npml, absorber="sponge", gamma_max=2.0)
+    g = op["gamma"]
+    assert np.all(g[npml:npml + n, npml:npml + n] == 0)
+    mid = npml + n // 2
+    assert np.allclose(g[npml - np.arange(1, npml + 1), mid], 2.0 * (np.arange(1, npml + 1) / npml) ** 2)
+    assert g[0, 0] == 2.0 and g.max() == 2.0
+    A = helmholtz.assemble(op)
+    assert abs(A - A.T).max() == 0
+    op0 = helmholtz.setup_operator(c, 10.0, 1.0 / n, 0, absorber="sponge")
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    lap = np.array([[0, -1, 0], [-1, 4, -1], [0, -1, 0]], dtype=float) * n * n
+    ref = ndi.correlate(u.real, lap, mode="constant") + 1j * ndi.correlate(u.imag, lap, mode="constant")
+    ref -= op0["k2"] * u
+    got = helmholtz.apply(op0, u)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
