@@ -24,6 +24,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3     # vector and matrix FP32
 PEAK_BF16_TFLOPS = 2500.0    # dense MFMA
 PEAK_FP64_TFLOPS = 78.6
+# iteration cap of the serving leg: the classical stand-in coefficients need
+# 200-750 iterations on these media
+SERVE_MAXIT = 1000
 
 
 def parse():
@@ -38,7 +41,7 @@ def parse():
                     help="right-hand sides of the solve-to-tolerance leg (0: skip)")
     ap.add_argument("--batched-iters", type=int, default=30,
                     help="iterations of the batched leg (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -220,7 +223,8 @@ def served_leg(nreq, rate, seed=3):
     model), 1-8 point-source right-hand sides per request, each solved to
     true relative residual 1e-6 with classical coefficients (random-init
     weights never converge).  Served: BF16 V-cycle convolutions through the
-    continuous-batching server (HBM budget 200 GB).  Comparator: the plain
+    continuous-batching server (HBM budget 200 GB), iteration cap 1000 for
+    both paths.  Comparator: the plain
     FP32 path, one right-hand side at a time in arrival order, on the same
     trace in real time.  Latency = arrival to the request's last solution."""
     import numpy as np
@@ -257,7 +261,7 @@ def served_leg(nreq, rate, seed=3):
         f = torch.from_numpy(synth.point_source(media[i]["n"], media[i]["npml"],
                                                 (0.5,) * dim, dim)).cuda()
         torch.cuda.synchronize()
-        srv.submit(mids[i], [f], [torch.zeros_like(f)], maxit=500)
+        srv.submit(mids[i], [f], [torch.zeros_like(f)], maxit=SERVE_MAXIT)
     torch.cuda.synchronize()
     got = 0
     while got < len(warm):
@@ -270,7 +274,7 @@ def served_leg(nreq, rate, seed=3):
     while len(done) < nreq:
         now = time.perf_counter() - t0
         while i < nreq and trace[i]["t"] <= now:
-            rid_of[srv.submit(mids[trace[i]["medium"]], fs[i], us[i], tol=1e-6, maxit=500)] = i
+            rid_of[srv.submit(mids[trace[i]["medium"]], fs[i], us[i], tol=1e-6, maxit=SERVE_MAXIT)] = i
             i += 1
         wait_ms = 20 if i >= nreq else max(0, min(20, int((trace[i]["t"] - now) * 1e3)))
         for c in srv.poll(64, wait_ms=wait_ms):
@@ -288,7 +292,7 @@ def served_leg(nreq, rate, seed=3):
     for dim, idx in warm.items():
         j = idx[0]
         f = torch.from_numpy(synth.point_source(media[j]["n"], media[j]["npml"], (0.5,) * dim, dim)).cuda()
-        hs[j].solve(f, torch.zeros_like(f), tol=1e-6, maxit=500, hist_cap=0)
+        hs[j].solve(f, torch.zeros_like(f), tol=1e-6, maxit=SERVE_MAXIT, hist_cap=0)
     torch.cuda.synchronize()
     lat_p, ok_p, its_p, worst_p = [], 0, 0, 0.0
     t0 = time.perf_counter()
@@ -298,7 +302,7 @@ def served_leg(nreq, rate, seed=3):
             time.sleep(r["t"] - now)
         for f in fs[k]:
             u[k].zero_()
-            info = hs[r["medium"]].solve(f, u[k], tol=1e-6, maxit=500, hist_cap=0)
+            info = hs[r["medium"]].solve(f, u[k], tol=1e-6, maxit=SERVE_MAXIT, hist_cap=0)
             ok_p += int(info["converged"])
             its_p += info["iters"]
             worst_p = max(worst_p, info["relres_true"])
@@ -328,27 +332,28 @@ def served_leg(nreq, rate, seed=3):
 
 def traffic_for(kernel):
     """Counter-measured HBM bytes per launch of `kernel` from the committed
-    rocprofv3 summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-    calibration); None when absent or when the kernel source changed since."""
+    rocprofv3 summaries profiles/traffic*.md (FETCH_SIZE + WRITE_SIZE, scaled
+    by the copy-kernel calibration); None when absent or when the kernel's
+    source changed since."""
+    import glob
     import hashlib
     import re
-    path = os.path.join(ROOT, "profiles", "traffic.md")
-    if not os.path.exists(path):
-        return None
-    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
-    if not m:
-        return None
-    try:
-        table = json.loads(m.group(1))
-    except ValueError:
-        return None
-    ent = table.get("kernels", {}).get(kernel)
-    if not ent:
-        return None
-    src = os.path.join(ROOT, ent["source"])
-    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != ent["sha256"]:
-        return None
-    return ent["bytes_per_launch"]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic*.md"))):
+        m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
+        if not m:
+            continue
+        try:
+            table = json.loads(m.group(1))
+        except ValueError:
+            continue
+        ent = table.get("kernels", {}).get(kernel)
+        if not ent:
+            continue
+        src = os.path.join(ROOT, ent["source"])
+        if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != ent["sha256"]:
+            return None
+        return ent["bytes_per_launch"]
+    return None
 
 
 def cpu_baseline(cfg, c, omega, h, f, tens, iters):

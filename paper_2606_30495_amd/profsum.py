@@ -2,7 +2,8 @@
 
     python3 -m paper_2606_30495_amd.profsum stats <kernel_stats.csv> [top]
     python3 -m paper_2606_30495_amd.profsum traffic --fetch <dir> --write <dir>
-        --cal-fetch <dir> --cal-write <dir> --cal-bytes B --kernel NAME=SOURCE ...
+        --cal-fetch <dir> --cal-write <dir> --cal-bytes B
+        [--kernel NAME=SOURCE ...] [--src NAME_PREFIX=SOURCE ...]
 
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 name, scales each by the calibration copy kernel's bytes-moved / counter
@@ -52,6 +53,7 @@ def counter_means(d, counter):
 
 def traffic(args):
     kv = dict(a.split("=", 1) for a in args["kernel"])
+    prefixes = [a.split("=", 1) for a in args["src"]]
     fetch, nf = counter_means(args["fetch"], "FETCH_SIZE")
     write, nw = counter_means(args["write"], "WRITE_SIZE")
     cf, _ = counter_means(args["cal_fetch"], "FETCH_SIZE")
@@ -70,8 +72,13 @@ def traffic(args):
         fb = fetch[k] * 1024.0 * sf
         wb = write.get(k, 0.0) * 1024.0 * sw
         lines.append(f"| `{k}` | {nf[k]} | {fetch[k]:.1f} | {write.get(k, 0.0):.1f} | {fb + wb:.4e} |")
-        if k in kv:
-            src = kv[k]
+        src = kv.get(k)
+        if src is None:
+            for pre, path in prefixes:
+                if k.startswith(pre):
+                    src = path
+                    break
+        if src is not None:
             sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
             table["kernels"][k] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                                    "source": os.path.relpath(src), "sha256": sha}
@@ -114,12 +121,12 @@ def main(argv):
         print(stats(argv[1], int(argv[2]) if len(argv) > 2 else 30))
         return
     if argv[0] == "traffic":
-        args = {"kernel": []}
+        args = {"kernel": [], "src": []}
         i = 1
         while i < len(argv):
             key = argv[i].lstrip("-").replace("-", "_")
-            if key == "kernel":
-                args["kernel"].append(argv[i + 1])
+            if key in ("kernel", "src"):
+                args[key].append(argv[i + 1])
             else:
                 args[key] = argv[i + 1]
             i += 2
