@@ -112,9 +112,16 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
   }
 }
 
+// Logical block t covers nodes [t HB HPT, (t + 1) HB HPT) and writes
+// partial[t]; physical blocks take logical ones in XCD-contiguous bands
+// (blockIdx % 8 walks one band), so the neighbour planes a block reads sit in
+// its own XCD's L2.  The grid is nb rounded up to a multiple of 8.
 template <int D, typename TIN>
-__global__ __launch_bounds__(HB) void helm_kernel(HArgs A) {
-  helm_body<D, TIN>(A, blockIdx.x);
+__global__ __launch_bounds__(HB) void helm_kernel(HArgs A, int nb) {
+  const int per = (nb + 7) / 8;
+  const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (t >= nb) return;
+  helm_body<D, TIN>(A, t);
 }
 
 template <int D, typename TIN>
@@ -139,10 +146,11 @@ hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLa
     else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<3, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
     else hipLaunchKernelGGL((helm_kernel_batched<3, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
   } else {
-    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel<2, double>), dim3(nb), dim3(HB), 0, s, *A);
-    else if (dim == 2) hipLaunchKernelGGL((helm_kernel<2, float>), dim3(nb), dim3(HB), 0, s, *A);
-    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel<3, double>), dim3(nb), dim3(HB), 0, s, *A);
-    else hipLaunchKernelGGL((helm_kernel<3, float>), dim3(nb), dim3(HB), 0, s, *A);
+    const unsigned g = (unsigned)((nb + 7) / 8 * 8);
+    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel<2, double>), dim3(g), dim3(HB), 0, s, *A, nb);
+    else if (dim == 2) hipLaunchKernelGGL((helm_kernel<2, float>), dim3(g), dim3(HB), 0, s, *A, nb);
+    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel<3, double>), dim3(g), dim3(HB), 0, s, *A, nb);
+    else hipLaunchKernelGGL((helm_kernel<3, float>), dim3(g), dim3(HB), 0, s, *A, nb);
   }
   return hipGetLastError();
 }

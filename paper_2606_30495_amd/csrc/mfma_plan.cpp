@@ -386,18 +386,19 @@ mcmg_status Ctx::plan_mfma() {
     }
   }
   // fused smoothing steps (one launch per step instead of three) on the 2D
-  // levels with 16 <= C <= 32, where one block computing t and u with halos
-  // beats three launches at every grid size measured; at C = 8 the halo
-  // recompute and at C = 64 the serial weight streaming make it slower.  The
-  // rule depends on C only, so all handles of a model share one launch
-  // schedule (the tile is autotuned).  MCMG_FUSED_STEP=0 keeps three
-  // launches everywhere, =2 fuses every C >= 8 level.
+  // bf16 levels with 16 <= C <= 32, where one block computing t and u with
+  // halos beats three launches at every grid size measured; at C = 8 the
+  // halo recompute, at C = 64 the serial weight streaming and with float32
+  // operands the heavier MFMA make it slower.  The rule depends on C and the
+  // precision only, so all handles of a model share one launch schedule (the
+  // tile is autotuned).  MCMG_FUSED_STEP=0 keeps three launches everywhere,
+  // =2 fuses every C >= 8 level in both precisions.
   const char* fz = getenv("MCMG_FUSED_STEP");
   const int fuse = fz ? atoi(fz) : 1;
   for (int l = 0; fuse && dim == 2 && l < L; ++l) {
     Level& lv = lev[l];
     if (lv.C < 8 || !lv.op_resid.on || !lv.op_mul.on || !lv.op_add.on || !lv.op_set.on) continue;
-    if (fuse == 1 && (lv.C < 16 || lv.C > 32)) continue;
+    if (fuse == 1 && (lv.C < 16 || lv.C > 32 || !bf)) continue;
     if (lv.m_sm.empty() || !lv.m_W || !lv.m_KA || !lv.m_KS) continue;
     const MOp& ro = lv.op_resid;
     const int nct = ro.ncols / 16;

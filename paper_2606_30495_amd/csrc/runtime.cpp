@@ -339,8 +339,8 @@ hipError_t Ctx::level1(Level& lv, int var, int step) {
     const double P = (double)lv.dims.total, T = dim == 2 ? 9.0 : 27.0;
     const double fl = var == L1_RESID ? 2.0 * T * 4 * 2 * P : 2.0 * T * 4 * (var == L1_FIRST ? 2 : 4) * P;
     const double by = var == L1_RESID ? 32.0 * P : (var == L1_FIRST ? 24.0 * P : 40.0 * P);
-    const char* name = intern_name(std::string("l1_kernel<") + std::to_string(dim) + ", " +
-                                   std::to_string(var) + ">");
+    const char* name = dim == 3 ? intern_name(std::string("l1z_kernel<") + std::to_string(var) + ">")
+                                : intern_name(std::string("l1_kernel<2, ") + std::to_string(var) + ">");
     e = timed(name, fl, by, [=] { return launch_level1(l, stream); });
   }
   if (e == hipSuccess && var != L1_RESID) std::swap(lv.e, lv.e_alt);

@@ -148,7 +148,7 @@ def test_fused_step_bitwise_equals_three_launches(name, precision, monkeypatch):
     p = problem(dim, n, npml, ch)
     r = synth.random_rhs((n + 2 * npml,) * dim, 9)
     out = []
-    for fused in ("1", "0"):
+    for fused in ("2", "0"):        # 2: fuse every C >= 8 level in both precisions
         monkeypatch.setenv("MCMG_FUSED_STEP", fused)
         H = handle(p, precision)
         z = to_dev(np.zeros_like(r))
