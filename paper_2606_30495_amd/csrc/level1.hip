@@ -37,101 +37,101 @@ namespace mcmg {
 namespace {
 
 template <int D> struct G1;
-template <> struct G1<2> { static constexpr int TZ = 1, TY = 32, TX = 64; };
+template <> struct G1<2> { static constexpr int TZ = 1, TY = 8, TX = 64; };
 // 3D z-streaming tile: TY x TX nodes per plane, ZC planes per block
 struct G3 { static constexpr int TY = 8, TX = 64, ZC = 32; };
 
 constexpr int NTH = 256;
 
-template <int D, int VAR>
+// A weight read from LDS is the same in every lane: moving it to a scalar
+// register keeps the vector registers for the points.
+__device__ __forceinline__ float uni(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+template <int D, int VAR, bool WL = false>
 __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, const int vblk) {
+  static_assert(D == 2, "3D uses the z-streaming form");
+  auto W_ = [](float v) { return WL ? uni(v) : v; };
   const float2* __restrict__ e = reinterpret_cast<const float2*>(A.e);
   float2* __restrict__ eo = reinterpret_cast<float2*>(A.eo);
   const float2* __restrict__ r = reinterpret_cast<const float2*>(A.r);
   const float2* __restrict__ a = reinterpret_cast<const float2*>(A.a);
   const float2* __restrict__ s = reinterpret_cast<const float2*>(A.s);
-  const Dims n = A.n;
-  const int tiles_x = A.tiles_x, tiles_y = A.tiles_y, tiles_z = A.tiles_z;
-  using G = G1<D>;
-  constexpr int T = (D == 2) ? 9 : 27;
+  using G = G1<2>;
+  constexpr int TY = G::TY, TX = G::TX;
   constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // halo of the staged e
-  constexpr int HZ = (D == 2) ? 0 : 1;                   // 2D has no z halo
-  // boxes: e (halo H), t (halo 2; RESID: the tile), u (halo 1), output tile
-  constexpr int EZ = G::TZ + 2 * H * HZ, EY = G::TY + 2 * H, EX = G::TX + 2 * H;
-  constexpr int TG = (VAR == L1_RESID) ? 0 : 2;
-  constexpr int TZt = G::TZ + 2 * TG * HZ, TYt = G::TY + 2 * TG, TXt = G::TX + 2 * TG;
-  constexpr int UZ = G::TZ + 2 * HZ, UY = G::TY + 2, UX = G::TX + 2;
-  constexpr int NE = EZ * EY * EX, NTB = TZt * TYt * TXt, NU = UZ * UY * UX;
-  constexpr int NO = G::TZ * G::TY * G::TX;
-  constexpr int PT = (NTB + NTH - 1) / NTH, PU = (NU + NTH - 1) / NTH, PO = (NO + NTH - 1) / NTH;
-  __shared__ float2 se[(VAR == L1_FIRST) ? 1 : NE];
-  __shared__ float2 st[(VAR == L1_RESID) ? 1 : NTB];
-  __shared__ float2 su[(VAR == L1_RESID) ? 1 : NU];
+  constexpr int EY = TY + 2 * H, EX = TX + 2 * H, NE = EY * EX;
+  constexpr int TG = (VAR == L1_RESID) ? 0 : 2;          // halo of the t box
+  constexpr int TYt = TY + 2 * TG, TXt = TX + 2 * TG, NT = TYt * TXt;
+  constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
+  constexpr int NO = TY * TX;
+  constexpr int RP = 4;                                   // points per thread per round
+  // LDS: `sa` holds e (halo H), then u (halo 1) once t exists; `sb` holds t.
+  constexpr int NA = (VAR == L1_FIRST) ? NU : (VAR == L1_RESID ? NE : (NE > NU ? NE : NU));
+  __shared__ float2 sa[NA];
+  __shared__ float2 sb[(VAR == L1_RESID) ? 1 : NT];
 
-  const int NX = (D == 2) ? n.n[1] : n.n[2], NY = (D == 2) ? n.n[0] : n.n[1];
-  const int NZ = (D == 2) ? 1 : n.n[0];
-  const int ntiles = tiles_x * tiles_y * tiles_z;
+  const int NX = A.n.n[1], NY = A.n.n[0];
+  const int ntiles = A.tiles_x * A.tiles_y;
   const int per = (ntiles + 7) / 8;
   const int tl = (vblk % 8) * per + vblk / 8;   // XCD-contiguous bands
   if (tl >= ntiles) return;
-  const int x0 = (tl % tiles_x) * G::TX, y0 = ((tl / tiles_x) % tiles_y) * G::TY;
-  const int z0 = (tl / (tiles_x * tiles_y)) * G::TZ;
-  auto inside = [&](int z, int y, int x) {
-    return x >= 0 && x < NX && y >= 0 && y < NY && z >= 0 && z < NZ;
-  };
-  auto gidx = [&](int z, int y, int x) { return ((long long)z * NY + y) * NX + x; };
+  const int x0 = (tl % A.tiles_x) * TX, y0 = (tl / A.tiles_x) * TY;
+  auto inside = [&](int y, int x) { return x >= 0 && x < NX && y >= 0 && y < NY; };
+  auto gidx = [&](int y, int x) { return (long long)y * NX + x; };
   const float2 zero = make_float2(0.f, 0.f);
 
-  // ---- stage e with halo H (all loads of a thread issued before the stores)
+  // ---- stage e with halo H (a batch of loads per thread, then the stores)
   if (VAR != L1_FIRST) {
     constexpr int PE = (NE + NTH - 1) / NTH;
-    const int oz = z0 - H * HZ, oy = y0 - H, ox = x0 - H;
-    float2 v[PE];
+#pragma unroll 1
+    for (int k0 = 0; k0 < PE; k0 += 8) {
+      float2 v[8];
 #pragma unroll
-    for (int k = 0; k < PE; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int x = i % EX, y = (i / EX) % EY, z = i / (EX * EY);
-      v[k] = (i < NE && inside(oz + z, oy + y, ox + x)) ? e[gidx(oz + z, oy + y, ox + x)] : zero;
-    }
+      for (int k = 0; k < 8; ++k) {
+        const int i = threadIdx.x + (k0 + k) * NTH;
+        const int y = i / EX, x = i % EX;
+        v[k] = (k0 + k < PE && i < NE && inside(y0 - H + y, x0 - H + x)) ? e[gidx(y0 - H + y, x0 - H + x)] : zero;
+      }
 #pragma unroll
-    for (int k = 0; k < PE; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      if (i < NE) se[i] = v[k];
+      for (int k = 0; k < 8; ++k) {
+        const int i = threadIdx.x + (k0 + k) * NTH;
+        if (k0 + k < PE && i < NE) sa[i] = v[k];
+      }
     }
     __syncthreads();
   }
 
-  // ---- t box: t = r - W*e - a (.) (KA*e)   (FIRST: t = r)
-  {
-    const int oz = z0 - TG * HZ, oy = y0 - TG, ox = x0 - TG;
-    float2 rv[PT], av[PT];
-    int eb[PT];                 // e-box index of the point (tap offset 0)
-    bool ok[PT];
+  // ---- t box: t = r - (W*e + a (.) (KA*e)) (FIRST: t = r; RESID: to memory)
+#pragma unroll 1
+  for (int r0 = 0; r0 < NT; r0 += NTH * RP) {
+    asm volatile("" ::: "memory");   // weights are re-read per round, not held in registers
+    float2 rv[RP], av[RP];
+    int eb[RP];
+    bool ok[RP];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int x = i % TXt, y = (i / TXt) % TYt, z = i / (TXt * TYt);
-      ok[k] = i < NTB && inside(oz + z, oy + y, ox + x);
-      const long long g = gidx(oz + z, oy + y, ox + x);
-      rv[k] = ok[k] ? r[g] : zero;
-      av[k] = (ok[k] && VAR != L1_FIRST) ? a[g] : zero;
-      // t-box point (z, y, x) sits at e-box (z + (H-TG) HZ, y + H - TG, x + H - TG)
-      eb[k] = (i < NTB) ? ((z + (H - TG) * HZ) * EY + (y + H - TG)) * EX + (x + H - TG) : (HZ * EY + 1) * EX + 1;
+    for (int k = 0; k < RP; ++k) {
+      const int i = r0 + threadIdx.x + k * NTH;
+      const int y = i / TXt, x = i % TXt;
+      const int gy = y0 - TG + y, gx = x0 - TG + x;
+      ok[k] = i < NT && inside(gy, gx);
+      rv[k] = ok[k] ? r[gidx(gy, gx)] : zero;
+      av[k] = (ok[k] && VAR != L1_FIRST) ? a[gidx(gy, gx)] : zero;
+      eb[k] = (i < NT) ? (y + H - TG) * EX + (x + H - TG) : EX + 1;
     }
-    float w0[PT], w1[PT], k0[PT], k1[PT];
+    float w0[RP], w1[RP], k0[RP], k1[RP];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
+    for (int k = 0; k < RP; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
     if (VAR != L1_FIRST) {
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
-        const int dx = t % 3 - 1;
-        const int to = (dz * EY + dy) * EX + dx;
-        const float a00 = w.W[0][0][t], a01 = w.W[0][1][t], a10 = w.W[1][0][t], a11 = w.W[1][1][t];
-        const float b00 = w.KA[0][0][t], b01 = w.KA[0][1][t], b10 = w.KA[1][0][t], b11 = w.KA[1][1][t];
+      for (int t = 0; t < 9; ++t) {
+        const int to = (t / 3 - 1) * EX + (t % 3 - 1);
+        const float a00 = W_(w.W[0][0][t]), a01 = W_(w.W[0][1][t]), a10 = W_(w.W[1][0][t]), a11 = W_(w.W[1][1][t]);
+        const float b00 = W_(w.KA[0][0][t]), b01 = W_(w.KA[0][1][t]), b10 = W_(w.KA[1][0][t]), b11 = W_(w.KA[1][1][t]);
 #pragma unroll
-        for (int k = 0; k < PT; ++k) {
-          const float2 v = se[eb[k] + to];
+        for (int k = 0; k < RP; ++k) {
+          const float2 v = sa[eb[k] + to];
           w0[k] = fmaf(a00, v.x, fmaf(a01, v.y, w0[k]));
           w1[k] = fmaf(a10, v.x, fmaf(a11, v.y, w1[k]));
           k0[k] = fmaf(b00, v.x, fmaf(b01, v.y, k0[k]));
@@ -139,102 +139,106 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
         }
       }
     }
-    if (VAR == L1_RESID) {
 #pragma unroll
-      for (int k = 0; k < PT; ++k) {
-        const int i = threadIdx.x + k * NTH;
-        const int x = i % TXt, y = (i / TXt) % TYt, z = i / (TXt * TYt);
-        if (ok[k])
-          eo[gidx(oz + z, oy + y, ox + x)] = make_float2(rv[k].x - w0[k] - av[k].x * k0[k],
-                                                         rv[k].y - w1[k] - av[k].y * k1[k]);
+    for (int k = 0; k < RP; ++k) {
+      const int i = r0 + threadIdx.x + k * NTH;
+      if (i >= NT) continue;
+      const float2 tv = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
+                              : zero;
+      if (VAR == L1_RESID) {
+        if (ok[k]) eo[gidx(y0 + i / TXt, x0 + i % TXt)] = tv;
+      } else {
+        sb[i] = tv;
       }
-      return;
     }
+  }
+  if (VAR == L1_RESID) return;
+  __syncthreads();
+
+  // ---- u box: u = s (.) (KS * t), into the e storage (e is not read again)
+#pragma unroll 1
+  for (int r0 = 0; r0 < NU; r0 += NTH * RP) {
+    asm volatile("" ::: "memory");
+    float2 sv[RP];
+    int tb[RP];
+    bool ok[RP];
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      if (i < NTB)
-        st[i] = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
-                      : zero;
+    for (int k = 0; k < RP; ++k) {
+      const int i = r0 + threadIdx.x + k * NTH;
+      const int y = i / UX, x = i % UX;
+      const int gy = y0 - 1 + y, gx = x0 - 1 + x;
+      ok[k] = i < NU && inside(gy, gx);
+      sv[k] = ok[k] ? s[gidx(gy, gx)] : zero;
+      tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
+    }
+    float c0[RP], c1[RP];
+#pragma unroll
+    for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int to = (t / 3 - 1) * TXt + (t % 3 - 1);
+      const float a00 = W_(w.KS[0][0][t]), a01 = W_(w.KS[0][1][t]), a10 = W_(w.KS[1][0][t]), a11 = W_(w.KS[1][1][t]);
+#pragma unroll
+      for (int k = 0; k < RP; ++k) {
+        const float2 v = sb[tb[k] + to];
+        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
+        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+      }
+    }
+    // every thread has finished reading e from sa (barrier above) before u lands there
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      const int i = r0 + threadIdx.x + k * NTH;
+      if (i < NU) sa[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
     }
   }
   __syncthreads();
 
-  // ---- u box: u = s (.) (KS * t)
-  {
-    const int oz = z0 - HZ, oy = y0 - 1, ox = x0 - 1;
-    float2 sv[PU];
-    int tb[PU];
-    bool ok[PU];
+  // ---- output tile: e' = e + Wsm * u (e re-read from memory: still in L2)
+#pragma unroll 1
+  for (int r0 = 0; r0 < NO; r0 += NTH * RP) {
+    asm volatile("" ::: "memory");
+    int ub[RP];
+    bool ok[RP];
+    float2 ev[RP];
 #pragma unroll
-    for (int k = 0; k < PU; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int x = i % UX, y = (i / UX) % UY, z = i / (UX * UY);
-      ok[k] = i < NU && inside(oz + z, oy + y, ox + x);
-      sv[k] = ok[k] ? s[gidx(oz + z, oy + y, ox + x)] : zero;
-      tb[k] = (i < NU) ? ((z + HZ) * TYt + (y + 1)) * TXt + (x + 1) : (HZ * TYt + 1) * TXt + 1;
+    for (int k = 0; k < RP; ++k) {
+      const int i = r0 + threadIdx.x + k * NTH;
+      const int y = i / TX, x = i % TX;
+      ok[k] = i < NO && inside(y0 + y, x0 + x);
+      ub[k] = (i < NO) ? (y + 1) * UX + (x + 1) : UX + 1;
+      ev[k] = (ok[k] && VAR != L1_FIRST) ? e[gidx(y0 + y, x0 + x)] : zero;
     }
-    float c0[PU], c1[PU];
+    float c0[RP], c1[RP];
 #pragma unroll
-    for (int k = 0; k < PU; ++k) c0[k] = c1[k] = 0.f;
+    for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
-      const int dx = t % 3 - 1;
-      const int to = (dz * TYt + dy) * TXt + dx;
-      const float a00 = w.KS[0][0][t], a01 = w.KS[0][1][t], a10 = w.KS[1][0][t], a11 = w.KS[1][1][t];
+    for (int t = 0; t < 9; ++t) {
+      const int to = (t / 3 - 1) * UX + (t % 3 - 1);
+      const float a00 = W_(w.Wsm[0][0][t]), a01 = W_(w.Wsm[0][1][t]), a10 = W_(w.Wsm[1][0][t]), a11 = W_(w.Wsm[1][1][t]);
 #pragma unroll
-      for (int k = 0; k < PU; ++k) {
-        const float2 v = st[tb[k] + to];
+      for (int k = 0; k < RP; ++k) {
+        const float2 v = sa[ub[k] + to];
         c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
         c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
       }
     }
 #pragma unroll
-    for (int k = 0; k < PU; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      if (i < NU) su[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
-    }
-  }
-  __syncthreads();
-
-  // ---- output tile: e' = e + Wsm * u
-  {
-    int ub[PO];
-    bool ok[PO];
-#pragma unroll
-    for (int k = 0; k < PO; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
-      ok[k] = i < NO && inside(z0 + z, y0 + y, x0 + x);
-      ub[k] = (i < NO) ? ((z + HZ) * UY + (y + 1)) * UX + (x + 1) : (HZ * UY + 1) * UX + 1;
-    }
-    float c0[PO], c1[PO];
-#pragma unroll
-    for (int k = 0; k < PO; ++k) c0[k] = c1[k] = 0.f;
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int dz = (D == 2) ? 0 : t / 9 - 1, dy = (D == 2) ? t / 3 - 1 : (t / 3) % 3 - 1;
-      const int dx = t % 3 - 1;
-      const int to = (dz * UY + dy) * UX + dx;
-      const float a00 = w.Wsm[0][0][t], a01 = w.Wsm[0][1][t], a10 = w.Wsm[1][0][t], a11 = w.Wsm[1][1][t];
-#pragma unroll
-      for (int k = 0; k < PO; ++k) {
-        const float2 v = su[ub[k] + to];
-        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
-        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < PO; ++k) {
-      const int i = threadIdx.x + k * NTH;
+    for (int k = 0; k < RP; ++k) {
       if (!ok[k]) continue;
-      const int x = i % G::TX, y = (i / G::TX) % G::TY, z = i / (G::TX * G::TY);
-      float2 ev = zero;
-      if (VAR != L1_FIRST) ev = se[((z + H * HZ) * EY + (y + H)) * EX + (x + H)];
-      eo[gidx(z0 + z, y0 + y, x0 + x)] = make_float2(ev.x + c0[k], ev.y + c1[k]);
+      const int i = r0 + threadIdx.x + k * NTH;
+      eo[gidx(y0 + i / TX, x0 + i % TX)] = make_float2(ev[k].x + c0[k], ev[k].y + c1[k]);
     }
   }
+}
+
+// Copy a weight set into LDS (all threads, then a barrier).
+__device__ __forceinline__ void stage_weights(const L1Weights* __restrict__ src, L1Weights* dst) {
+  constexpr int NW = sizeof(L1Weights) / sizeof(float);
+  const float* s = reinterpret_cast<const float*>(src);
+  float* d = reinterpret_cast<float*>(dst);
+  for (int i = threadIdx.x; i < NW; i += NTH) d[i] = s[i];
+  __syncthreads();
 }
 
 // Ring slot of plane `pl` (pl >= -4 R) in a ring of R planes.
@@ -481,7 +485,12 @@ __global__ __launch_bounds__(NTH) void l1_kernel_batched(const L1Args* __restric
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
   const L1Args A = tab[batch_entry(row, np, p)];
-  l1_body<D, VAR>(A, *A.wp, blockIdx.x - pre[p]);
+  // the problem's weights (1.7 KB) are staged in LDS once per block and read
+  // there with uniform addresses (through the table pointer they would be
+  // vector loads held in registers)
+  __shared__ L1Weights wsh;
+  stage_weights(A.wp, &wsh);
+  l1_body<D, VAR, true>(A, wsh, blockIdx.x - pre[p]);
 }
 
 template <int D, int VAR>
