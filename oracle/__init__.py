@@ -15,8 +15,11 @@ Modules:
   mcmg      -- the learnable setup (Alg. 1) and the V-cycle MG(r) (Alg. 2).
   krylov    -- right-preconditioned restarted FGMRES(m) and the stationary
                McMg iteration (Sec. 3.3 Eq. mcmg_iteration).
+  born      -- the periodic operator, the discrete Green operator
+               (Eq. discrete_symbol) and the Born-series iterations: CBS
+               (Eq. cbs_eq, Eq. cbs_gamma) and Born+McMg.
 
 Parity status per function is stated in each module header.  Readings of the
 paper where it is silent are listed at the top of each module.
 """
-from . import helmholtz, conv, mcmg, krylov  # noqa: F401
+from . import helmholtz, conv, mcmg, krylov, born  # noqa: F401
