@@ -127,6 +127,55 @@ mcmg_status mcmg_solve(mcmg_handle h, const double* f, double* u, double tol,
 mcmg_status mcmg_stationary(mcmg_handle h, const double* f, double* u,
                             double tol, int maxit, mcmg_info* info);
 
+/* ---- Born-series form (appendix on the Born-series variant; appendix on
+ * the discrete Green operator, Eq. discrete_symbol) ----------------------
+ *
+ * The Born solvers act on the PERIODIC operator of the extended grid,
+ *   A_per u = -Lap_h^per u - k^2 (1 + i gamma) u,
+ * which the FFT diagonalises exactly.  They need the sponge layer
+ * (MCMG_ABL_SPONGE) or npml = 0; a PML stretches the Laplacian and is
+ * rejected with MCMG_E_ARG.  Each extended side must lie in [2, 5120].
+ *
+ * The background uses the CBS parameters (Eq. cbs_gamma):
+ *   k0^2 = (min k^2 + max k^2) / 2,
+ *   V    = k^2 (1 + i gamma) - k0^2,
+ *   eps  = max |V|.
+ * The Green operator carries the same absorption:
+ *   G = (-Lap_h^per - k0^2 - i eps)^{-1}.
+ * The Born-series residual is G (f - A_per u). */
+enum { MCMG_BORN_MCMG = 0, MCMG_BORN_CBS = 1 };
+
+/* Fix the background (k0sq > 0, eps > 0), or take the defaults above for
+ * a value <= 0 (found by device reductions).  The first Born call on a
+ * handle without this call uses the defaults.  Builds the per-axis FFT
+ * tables once (a few n_a-long device arrays owned by the handle).  Blocks.
+ * Errors: E_ARG (a PML, a side out of range, eps = 0 for a constant medium
+ * with no sponge), E_OOM, E_HIP. */
+mcmg_status mcmg_born_setup(mcmg_handle h, double k0sq, double eps);
+
+/* The background in use (sets up the defaults first if needed). */
+mcmg_status mcmg_born_params(mcmg_handle h, double* k0sq, double* eps);
+
+/* y = G x: FFT, divide by sum_a (4/h^2) sin^2(pi m_a / n_a) - k0^2 - i eps,
+ * then the inverse FFT, all in FP64.  x, y: device complex128 on the
+ * extended grid; they may alias.  Asynchronous on the handle's stream. */
+mcmg_status mcmg_born_green(mcmg_handle h, const double* x, double* y);
+
+/* Au = A_per u in FP64.  u, Au: device complex128; may not alias.
+ * Asynchronous. */
+mcmg_status mcmg_born_matvec(mcmg_handle h, const double* u, double* Au);
+
+/* Born-series iteration u <- u + P(G (f - A_per u)):
+ *   method MCMG_BORN_MCMG: P = MG, one V-cycle in the handle's precision
+ *     (Born+McMg);
+ *   method MCMG_BORN_CBS: P = gamma (.), gamma = 1 + i V / eps
+ *     (Eq. cbs_eq).
+ * It stops when the FP64 true residual |f - A_per u| <= tol |f|, or after
+ * maxit updates (MCMG_NOT_CONVERGED).  f, u: device complex128 (u in/out).
+ * info (iters, relres_true, hist) may be NULL.  Blocks until done. */
+mcmg_status mcmg_born_solve(mcmg_handle h, int method, const double* f, double* u,
+                            double tol, int maxit, mcmg_info* info);
+
 /* Batched FGMRES (many media and right-hand sides, uneven sizes, advanced
  * together, one launch per operation for the whole batch).  hs[i] is the
  * handle of problem i (the same handle may appear several times); f[i],

@@ -35,6 +35,7 @@ class Pml(ctypes.Structure):
 
 
 ABSORBER = {"pml": 0, "sponge": 1}
+BORN_MCMG, BORN_CBS = 0, 1
 
 
 class Weights(ctypes.Structure):
@@ -84,6 +85,14 @@ EXPORTS = {
                                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
     "mcmg_stationary": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
+    "mcmg_born_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
+    "mcmg_born_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "mcmg_born_green": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mcmg_born_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mcmg_born_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                       ctypes.POINTER(Info)]),
     "mcmg_solve_batch": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p),
                                         ctypes.POINTER(ctypes.c_void_p),
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
@@ -225,6 +234,29 @@ class Handle:
 
     def stationary(self, f, u, tol=1e-6, maxit=500, hist_cap=4096):
         return self._solve(lib().mcmg_stationary, f, u, tol, maxit, hist_cap)
+
+    # ---- Born-series form (periodic operator, discrete Green operator) ----
+    def born_setup(self, k0sq=0.0, eps=0.0):
+        _check(lib().mcmg_born_setup(self.ptr, float(k0sq), float(eps)))
+
+    def born_params(self):
+        k0sq, eps = ctypes.c_double(), ctypes.c_double()
+        _check(lib().mcmg_born_params(self.ptr, ctypes.byref(k0sq), ctypes.byref(eps)))
+        return k0sq.value, eps.value
+
+    def born_green(self, x, y):
+        self._shape_check(x, y)
+        _check(lib().mcmg_born_green(self.ptr, _ptr(x), _ptr(y)))
+
+    def born_matvec(self, u, Au):
+        self._shape_check(u, Au)
+        _check(lib().mcmg_born_matvec(self.ptr, _ptr(u), _ptr(Au)))
+
+    def born_solve(self, f, u, method="mcmg", tol=1e-6, maxit=500, hist_cap=4096):
+        m = {"mcmg": BORN_MCMG, "cbs": BORN_CBS}[method]
+        fn = lib().mcmg_born_solve
+        return self._solve(lambda h, fp, up, t, mi, inf: fn(h, m, fp, up, t, mi, inf),
+                           f, u, tol, maxit, hist_cap)
 
     def prof_enable(self, on=True):
         _check(lib().mcmg_prof_enable(self.ptr, 1 if on else 0))

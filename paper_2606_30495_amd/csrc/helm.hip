@@ -6,10 +6,11 @@
 //           - k_I^2 (1 + i gamma_I) u_I
 // with cm_a = 1/(h^2 s_a(I) s_a(I-1/2)), cp_a = 1/(h^2 s_a(I) s_a(I+1/2))
 // (divergence form of the stretched Laplacian; Dirichlet zero outside the
-// extended grid).  PML: gamma = 0; sponge: s = 1 and gamma = gmax min(1,
-// sum_a g_a[I_a]) from per-axis tables.  Per node it streams u (16 B), k^2 (8 B) and the output
-// (16 B); the residual form also reads f (16 B) and emits block partial sums
-// of |f - A u|^2 for the FP64 norm.
+// extended grid, or periodic wrap-around for the Born form).  PML: gamma = 0;
+// sponge: s = 1 and gamma = gmax min(1, sum_a g_a[I_a]) from per-axis tables.
+// Per node it streams u (16 B), k^2 (8 B) and the output (16 B); the
+// residual form also reads f (16 B) and emits block partial sums of
+// |f - A u|^2 for the FP64 norm.
 #include "internal.h"
 
 namespace mcmg {
@@ -90,8 +91,11 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
       const cplx m = ld(cms[ax], i[ax]);
       const cplx pc = ld(cps[ax], i[ax]);
       cplx um = {0.0, 0.0}, up = {0.0, 0.0};
+      const long long wrap = (long long)(n.n[ax] - 1) * stride[ax];
       if (i[ax] > 0) um = ld(u, p - stride[ax]);
+      else if (A.op.periodic) um = ld(u, p + wrap);
       if (i[ax] < n.n[ax] - 1) up = ld(u, p + stride[ax]);
+      else if (A.op.periodic) up = ld(u, p - wrap);
       const cplx d = {m.re + pc.re, m.im + pc.im};
       const cplx t0 = cmul(d, uc), t1 = cmul(m, um), t2 = cmul(pc, up);
       acc.re += t0.re - t1.re - t2.re;

@@ -82,6 +82,7 @@ struct HelmOp {
   // sponge layer: diagonal -k^2 (1 + i gamma), gamma = gmax min(1, sum_a g_a[i_a])
   double gmax;            // 0: no sponge term
   const double* g[3];     // [n_a] squared normalised distance into the layer
+  int periodic = 0;       // 1: neighbours wrap around every axis (Born form)
 };
 
 // out = A u (f == nullptr) or out = f - A u; if partial != nullptr the
@@ -270,4 +271,47 @@ struct HArgs {
   double* partial;
 };
 hipError_t launch_helm_batched(int dim, int tin, const BatchLaunch& b, hipStream_t s);
+}  // namespace mcmg
+
+namespace mcmg {
+// ---- Born series: discrete Green operator by FFT ---------------------------
+constexpr int FFT_MAXL = 5120;   // longest axis (elements per block <= FFT_MAXL)
+constexpr int FFT_MAXST = 16;    // radix stages
+enum { FFT_FWD = 0, FFT_SYM = 1, FFT_INV = 2, FFT_LAST = 3 };
+// One axis pass over a complex FP64 field (row-major, axis of length L and
+// stride S; `outer` = number of lines (contiguous) or of outer indices
+// (strided)).  src and dst may alias.
+struct FftArgs {
+  const double* src;
+  double* dst;
+  const double2* tw;       // exp(-2 pi i j / L), j < L
+  const int* rev;          // digit-reversed position of natural index j
+  int L, TC, contiguous, nst;
+  long long S, outer;
+  int rad[FFT_MAXST], mlen[FFT_MAXST];   // radix and sub-length of each stage
+  // SYM: symbol tables d_a (length n_a), extended sizes, background
+  const double* d[3];
+  int n[3], dim;
+  double k0sq, eps;
+  // LAST: scale and, for the CBS update, u and the damped k^2
+  double scale;
+  double* u;
+  const double* k2;
+  const double* g[3];
+  double gmax;
+};
+size_t fft_lds_bytes(const FftArgs& a);
+long long fft_blocks(const FftArgs& a);
+hipError_t launch_fft(int mode, const FftArgs& a, hipStream_t s);
+
+struct BornStatsArgs {
+  const double* k2;
+  const double* g[3];
+  double gmax, k0sq;
+  int n[3], dim;
+  long long N;
+  double* out;             // [2 * blocks]: (min, max) per block
+};
+int born_stats_blocks(long long n);
+hipError_t launch_born_stats(const BornStatsArgs& a, int pass, hipStream_t s);
 }  // namespace mcmg

@@ -107,6 +107,22 @@ struct HostTensor {
   std::vector<float> w;
 };
 
+// Born-series state: background, per-axis FFT plans and symbol tables.
+struct BornAxis {
+  int n = 1;
+  std::vector<int> rad;      // radices in stage order
+  double2* tw = nullptr;     // device exp(-2 pi i j / n)
+  int* rev = nullptr;        // device digit-reversal table
+  double* d = nullptr;       // device (4/h^2) sin^2(pi m / n)
+};
+struct BornState {
+  bool ready = false;
+  double k0sq = 0, eps = 0;
+  BornAxis ax[3];
+  double* stats = nullptr;   // reduction partials
+  int nstats = 0;
+};
+
 struct Ctx {
   int dim = 2;
   int nint[3] = {1, 1, 1};
@@ -194,6 +210,12 @@ struct Ctx {
   hipError_t run_setup();
   HelmOp helm() const;
   hipError_t helm_timed(int tin, const void* u, const double* f, double* out, double* partial);
+
+  // Born series (born.cpp)
+  BornState born;
+  mcmg_status born_setup(double k0sq, double eps);
+  hipError_t green(const double* x, double* y, double* u_cbs);   // y = G x, or u += gamma G x
+  hipError_t helm_periodic(const double* u, const double* f, double* out, double* partial);
 };
 
 }  // namespace mcmg

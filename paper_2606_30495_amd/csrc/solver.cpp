@@ -204,9 +204,65 @@ mcmg_status stationary(Ctx* c, const double* f, double* u, double tol, int maxit
   }
 }
 
+// Born-series iteration (appendix on the Born-series variant):
+//   u <- u + P(G (f - A_per u)),  P = MG (Born+McMg) or gamma (.) (CBS, Eq. cbs_eq),
+// with the true periodic residual |f - A_per u| <= tol |f| as the stop test.
+// The residual, G and the update run in FP64; MG in the handle's precision.
+mcmg_status born_solve(Ctx* c, int method, const double* f, double* u, double tol, int maxit,
+                       mcmg_info* info) {
+  Finish fin{info};
+  if (!f || !u) return fin.done(fail(MCMG_E_ARG, "null f or u"));
+  if (!(tol > 0) || maxit < 0) return fin.done(fail(MCMG_E_ARG, "bad tol/maxit"));
+  if (method != MCMG_BORN_MCMG && method != MCMG_BORN_CBS)
+    return fin.done(fail(MCMG_E_ARG, "unknown Born preconditioner %d", method));
+  if (!c->born.ready) {
+    const mcmg_status st = c->born_setup(0.0, 0.0);
+    if (st != MCMG_OK) return fin.done(st);
+  }
+  hipStream_t s = c->stream;
+  const long long N = c->ext.total;
+  HCK(norm_sq(c, f, c->scal + 0));
+  HCK(read_scal(c, 0, 1));
+  const double fnorm = std::sqrt(c->host_scal[0]);
+  if (!std::isfinite(fnorm)) return fin.done(fail(MCMG_E_NONFINITE, "non-finite right-hand side"));
+  if (fnorm == 0.0) {
+    HCK(launch_zero_f64(u, 2 * N, s));
+    HCK(hipStreamSynchronize(s));
+    return fin.done(MCMG_OK);
+  }
+  HelmOp op = c->helm();
+  int its = 0;
+  while (true) {
+    HCK(c->helm_periodic(u, f, c->rv, c->partial));
+    HCK(launch_reduce_sum(c->partial, helm_blocks(op), c->scal + 2, s));
+    HCK(read_scal(c, 3, 1));
+    const double beta = c->host_scal[0];
+    fin.iters = its;
+    fin.relres_true = beta / fnorm;
+    fin.hist.push_back(beta / fnorm);
+    if (!std::isfinite(beta)) return fin.done(fail(MCMG_E_NONFINITE, "non-finite residual"));
+    if (beta <= tol * fnorm) return fin.done(MCMG_OK);
+    if (its >= maxit) return fin.done(MCMG_NOT_CONVERGED);
+    if (method == MCMG_BORN_CBS) {
+      HCK(c->green(c->rv, c->rv, u));
+    } else {
+      HCK(c->green(c->rv, c->rv, nullptr));
+      HCK(c->vcycle(c->rv, T_F64, c->zt, T_F32));
+      HCK(launch_axpy_f32(c->zt, u, N, s));
+    }
+    ++its;
+  }
+}
+
 }  // namespace mcmg
 
 extern "C" {
+
+mcmg_status mcmg_born_solve(mcmg_handle h, int method, const double* f, double* u, double tol,
+                            int maxit, mcmg_info* info) {
+  if (!h) return fail(MCMG_E_ARG, "null handle");
+  return born_solve((Ctx*)h, method, f, u, tol, maxit, info);
+}
 
 mcmg_status mcmg_solve(mcmg_handle h, const double* f, double* u, double tol, int maxit,
                        mcmg_info* info) {
