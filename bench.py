@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--born-iters", type=int, default=20,
+                    help="Born-series steps per method in the Born leg (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     return ap.parse_args()
@@ -383,6 +385,54 @@ def cpu_baseline(cfg, c, omega, h, f, tens, iters):
                       f"elementwise work single-threaded; host {os.cpu_count()} CPUs"}
 
 
+def born_leg(cfg, c, omega, h, f, blob, precision, iters):
+    """Born-series form on the same medium with a sponge layer of the same
+    width: Born+McMg (u <- u + MG(G(f - A_per u)), G by FFT) and CBS, each
+    run for `iters` steps from u = 0, plus the FFT passes' HIP-event timing.
+    The iteration count is fixed (random-init weights), so the leg measures
+    the cost per Born step."""
+    import torch
+    from paper_2606_30495_amd import Handle
+    H = Handle(c, omega, h, cfg.npml, blob, precision=precision, restart=2, absorber="sponge")
+    H.born_setup()
+    k0sq, eps = H.born_params()
+    fd = torch.from_numpy(f).to("cuda")
+    ud = torch.zeros_like(fd)
+    out = {"workload": f"{cfg.name} with a {cfg.npml}-cell sponge layer, periodic Born operator",
+           "precision": precision, "k0sq": k0sq, "eps": eps}
+    for method in ("mcmg", "cbs"):
+        H.born_solve(fd, ud, method=method, tol=1e-300, maxit=2, hist_cap=0)   # warm-up
+        ud.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = H.born_solve(fd, ud, method=method, tol=1e-300, maxit=iters, hist_cap=0)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[method] = {"iters_per_s": round(info["iters"] / el, 3),
+                       "ms_per_step": round(el / max(info["iters"], 1) * 1e3, 4)}
+    ud.zero_()
+    H.prof_enable(True)
+    H.born_solve(fd, ud, method="mcmg", tol=1e-300, maxit=iters, hist_cap=0)
+    recs = H.prof_report()
+    fft = []
+    for r in sorted(recs, key=lambda r: r["name"]):
+        if not r["name"].startswith("fft_kernel"):
+            continue
+        replay_ms, _ = H.prof_replay(r["name"], reps=3)
+        gbs = r["bytes_per_launch"] / (replay_ms * 1e-3) / 1e9
+        fft.append({"kernel": r["name"], "launches_per_step": round(r["launches"] / iters, 2),
+                    "avg_launch_us": round(replay_ms * 1e3, 3), "achieved_gbs": round(gbs, 1),
+                    "frac_hbm": round(gbs / PEAK_HBM_GBS, 4),
+                    "bytes_per_launch": r["bytes_per_launch"]})
+    H.prof_enable(False)
+    out["fft"] = fft
+    tot = sum(r["total_ms"] for r in recs)
+    out["fft_share_of_step"] = round(sum(r["total_ms"] for r in recs
+                                         if r["name"].startswith("fft_kernel")) / max(tot, 1e-9), 4)
+    H.close()
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -433,6 +483,8 @@ def main():
         line["batched"] = batched_leg(a.precision, a.batched_iters)
     if a.serve_requests > 0:
         line["served"] = served_leg(a.serve_requests, a.serve_rate)
+    if a.born_iters > 0 and cfg.dim == 2:
+        line["born"] = born_leg(cfg, c, omega, h, f, blob, a.precision, a.born_iters)
     if cmp_leg is not None:
         line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
                            "ms_per_step": round(cmp_leg["ms_per_step"], 4),

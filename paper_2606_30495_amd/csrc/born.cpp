@@ -85,7 +85,15 @@ mcmg_status Ctx::born_setup(double k0sq_in, double eps_in) {
         const double sn = std::sin(M_PI * (double)j / (double)X.n);
         d[j] = 4.0 / (h * h) * sn * sn;
       }
+      std::vector<int> plan(2 * X.rad.size());
+      int ml = 1;
+      for (size_t st = 0; st < X.rad.size(); ++st) {
+        plan[2 * st] = X.rad[st];
+        plan[2 * st + 1] = ml;
+        ml *= X.rad[st];
+      }
       if ((e = upload(this, tw, &X.tw)) != hipSuccess ||
+          (e = upload(this, plan, &X.plan)) != hipSuccess ||
           (e = upload(this, digit_reversal(X.n, X.rad), &X.rev)) != hipSuccess ||
           (e = upload(this, d, &X.d)) != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? MCMG_E_OOM : MCMG_E_HIP, "Born tables: %s",
@@ -166,26 +174,26 @@ hipError_t Ctx::green(const double* x, double* y, double* u_cbs) {
     A.rev = X.rev;
     A.L = X.n;
     A.nst = (int)X.rad.size();
-    int m = 1;
+    A.plan = X.plan;
     double cmacs = 0;
+    A.rc = FFT_RC_SMALL;
     for (int s = 0; s < A.nst; ++s) {
-      A.rad[s] = X.rad[s];
-      A.mlen[s] = m;
-      m *= X.rad[s];
       cmacs += X.rad[s];
+      if (X.rad[s] == 11) A.rc = std::max(A.rc, (int)FFT_RC_11);
+      else if (X.rad[s] > 7) A.rc = FFT_RC_ANY;
     }
     long long S = 1, O = 1;
     for (int b = a + 1; b < D; ++b) S *= next[b];
     for (int b = 0; b < a; ++b) O *= next[b];
     A.S = S;
     A.contiguous = S == 1;
-    if (A.contiguous) {
-      A.outer = tot / X.n;
-      A.TC = std::max(1, std::min(16, 2048 / X.n));
-    } else {
-      A.outer = O;
-      A.TC = std::max(1, std::min(16, FFT_MAXL / X.n));
-    }
+    // about 3072 elements per block: measured best on 1056^2 and 216^3
+    // (more lines per block cut the grid below two blocks per CU, fewer
+    // leave threads idle in the butterfly stages)
+    constexpr int kElems = 3072;
+    A.outer = A.contiguous ? tot / X.n : O;
+    A.TC = std::max(1, std::min(16, kElems / X.n));
+    A.tw_lds = ((size_t)A.TC * (X.n + 1) + X.n) * 16 <= FFT_MAXLDS ? 1 : 0;
     for (int b = 0; b < 3; ++b) {
       A.d[b] = b < D ? born.ax[b].d : nullptr;
       A.n[b] = b < D ? next[b] : 1;

@@ -277,7 +277,10 @@ namespace mcmg {
 // ---- Born series: discrete Green operator by FFT ---------------------------
 constexpr int FFT_MAXL = 5120;   // longest axis (elements per block <= FFT_MAXL)
 constexpr int FFT_MAXST = 16;    // radix stages
+constexpr size_t FFT_MAXLDS = 160 * 1024;
 enum { FFT_FWD = 0, FFT_SYM = 1, FFT_INV = 2, FFT_LAST = 3 };
+// radix classes: radices in {2, 3, 4, 5, 7}; also 11; anything
+enum { FFT_RC_SMALL = 0, FFT_RC_11 = 1, FFT_RC_ANY = 2 };
 // One axis pass over a complex FP64 field (row-major, axis of length L and
 // stride S; `outer` = number of lines (contiguous) or of outer indices
 // (strided)).  src and dst may alias.
@@ -287,8 +290,10 @@ struct FftArgs {
   const double2* tw;       // exp(-2 pi i j / L), j < L
   const int* rev;          // digit-reversed position of natural index j
   int L, TC, contiguous, nst;
+  int tw_lds;              // 1: stage the twiddle table in LDS
+  int rc;                  // radix class (FFT_RC_*)
   long long S, outer;
-  int rad[FFT_MAXST], mlen[FFT_MAXST];   // radix and sub-length of each stage
+  const int* plan;         // device [2 nst]: radix, then sub-length, of each stage
   // SYM: symbol tables d_a (length n_a), extended sizes, background
   const double* d[3];
   int n[3], dim;

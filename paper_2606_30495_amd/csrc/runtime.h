@@ -111,6 +111,7 @@ struct HostTensor {
 struct BornAxis {
   int n = 1;
   std::vector<int> rad;      // radices in stage order
+  int* plan = nullptr;       // device (radix, sub-length) per stage
   double2* tw = nullptr;     // device exp(-2 pi i j / n)
   int* rev = nullptr;        // device digit-reversal table
   double* d = nullptr;       // device (4/h^2) sin^2(pi m / n)
