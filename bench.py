@@ -433,6 +433,10 @@ def born_leg(cfg, c, omega, h, f, blob, precision, iters):
     return out
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -449,8 +453,11 @@ def main():
     blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
 
     head = run_leg(cfg, c, omega, h, f, blob, a.precision, a.steps, a.warmup)
+    progress(f"{a.precision} leg: {head['value']:.1f} iters/s")
     other = "fp32" if a.precision == "bf16" else "bf16"
     cmp_leg = None if a.single else run_leg(cfg, c, omega, h, f, blob, other, a.steps, a.warmup)
+    if cmp_leg is not None:
+        progress(f"{other} leg: {cmp_leg['value']:.1f} iters/s")
     recs = head["recs"]
     dom = recs[0]
     roof = roofline_for(dom, a.precision)
@@ -479,18 +486,23 @@ def main():
         line["solves"] = [solves_leg(a.precision, a.solves)]
         if not a.single:
             line["solves"].append(solves_leg(other, a.solves))
+        progress("solve-to-tolerance legs done")
     if a.batched_iters > 0:
         line["batched"] = batched_leg(a.precision, a.batched_iters)
+        progress("batched leg done")
     if a.serve_requests > 0:
         line["served"] = served_leg(a.serve_requests, a.serve_rate)
+        progress("served leg done")
     if a.born_iters > 0 and cfg.dim == 2:
         line["born"] = born_leg(cfg, c, omega, h, f, blob, a.precision, a.born_iters)
+        progress("Born leg done")
     if cmp_leg is not None:
         line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
                            "ms_per_step": round(cmp_leg["ms_per_step"], 4),
                            "relres_true": cmp_leg["info"]["relres_true"],
                            "dominant_kernel": cmp_leg["recs"][0]["name"]}
     if not a.no_cpu:
+        progress("CPU oracle baseline ...")
         line["cpu_baseline"] = cpu_baseline(cfg, c, omega, h, f, tens, a.cpu_iters)
     else:
         line["cpu_baseline"] = None

@@ -209,7 +209,9 @@ hipError_t Ctx::green(const double* x, double* y, double* u_cbs) {
     const double n = (double)tot;
     const double flops = n * 8.0 * cmacs * (mode == FFT_SYM ? 2.0 : 1.0);
     const double bytes = (mode == FFT_LAST && u_cbs) ? n * 56.0 : n * 32.0;
-    const char* name = intern_name("fft_kernel<" + std::to_string(mode) + ">");
+    const char* name = intern_name("fft_kernel<" + std::to_string(mode) + ", " +
+                                   std::to_string(A.rc) + ", " + (A.tw_lds ? "true" : "false") +
+                                   ">");
     return timed(name, flops, bytes, [=] { return launch_fft(mode, A, stream); });
   };
   hipError_t e;
