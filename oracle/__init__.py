@@ -15,6 +15,9 @@ Modules:
   mcmg      -- the learnable setup (Alg. 1) and the V-cycle MG(r) (Alg. 2).
   krylov    -- right-preconditioned restarted FGMRES(m) and the stationary
                McMg iteration (Sec. 3.3 Eq. mcmg_iteration).
+  train     -- the residual loss L_H (Eq. loss_fun) and its gradient by
+               float64 reverse mode over an independent torch forward, Adam,
+               LLPF level growth (Sec. llpf).
   born      -- the periodic operator, the discrete Green operator
                (Eq. discrete_symbol) and the Born-series iterations: CBS
                (Eq. cbs_eq, Eq. cbs_gamma) and Born+McMg.
@@ -23,3 +26,4 @@ Parity status per function is stated in each module header.  Readings of the
 paper where it is silent are listed at the top of each module.
 """
 from . import helmholtz, conv, mcmg, krylov, born  # noqa: F401
+# oracle.train imports torch; it is loaded on use (import oracle.train)
