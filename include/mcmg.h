@@ -127,6 +127,60 @@ mcmg_status mcmg_solve(mcmg_handle h, const double* f, double* u, double tol,
 mcmg_status mcmg_stationary(mcmg_handle h, const double* f, double* u,
                             double tol, int maxit, mcmg_info* info);
 
+/* ---- Training (training section, Eq. loss_fun; Sec. llpf) ----------------
+ *
+ * The loss of a batch of B samples (handle i: medium k_i, device residual
+ * r_i, complex128 on that handle's extended grid) is
+ *   L_H = (1/B) sum_i |A_i MG(k_i, r_i) - r_i| / |r_i|.
+ * A is applied in FP64 and MG in float32 with the VALU convolutions of
+ * Alg. 1 and Alg. 2.  The gradient comes from reverse accumulation through
+ * the setup network and the V-cycle, with A^H for the loss.
+ *
+ * Parameters use the canonical tensor order and layout of the weight blob,
+ * as one float32 vector.  hs[0] owns them, together with the Adam moments;
+ * the other handles of a batch must hold the same model (dim, levels,
+ * channels, smoothing counts; any media and grid sizes) and get the master's
+ * parameters at the start of each step.  After training, mcmg_train_commit
+ * refreshes the forms the fast solve path derives from the weights
+ * (matrix-core packs, level-1 sweep weights, cached features).  Until then,
+ * apply and solve on a trained handle see stale matrix-core weights.
+ * Training state is allocated on first use and owned by the handle.  The
+ * handles' streams are synchronised; every call blocks. */
+typedef struct {
+  double lr;       /* > 0 */
+  double beta1;    /* [0, 1), 0.9 */
+  double beta2;    /* [0, 1), 0.999 */
+  double eps;      /* > 0, 1e-8 */
+} mcmg_adam;
+
+/* One Adam step on hs[0]'s parameters from the gradient of L_H over the nh
+ * samples (hs[i], r[i]); *loss (may be NULL) receives L_H before the
+ * update.  Frozen tensors keep their values and moments.  Errors: E_ARG
+ * (models differ, bad Adam parameters), E_NONFINITE (|r_i| = 0 or a
+ * non-finite loss), E_OOM, E_HIP. */
+mcmg_status mcmg_train_step(mcmg_handle* hs, int nh, const double* const* r,
+                            const mcmg_adam* opt, double* loss);
+
+/* L_H and its gradient (host float32 vector of ngrad = the model's float
+ * count, canonical order) without an update. */
+mcmg_status mcmg_train_loss_grad(mcmg_handle* hs, int nh, const double* const* r,
+                                 double* loss, float* grad, size_t ngrad);
+
+/* LLPF: mask[i] != 0 makes canonical tensor i trainable, 0 freezes it
+ * (ntensors = the model's tensor count). */
+mcmg_status mcmg_train_set_trainable(mcmg_handle h, const int* mask, int ntensors);
+
+/* Re-derive the fast-path weight forms and the cached features from the
+ * trained parameters. */
+mcmg_status mcmg_train_commit(mcmg_handle h);
+
+/* Tensor and float counts of the handle's model. */
+mcmg_status mcmg_weights_size(mcmg_handle h, int* ntensors, size_t* nfloats);
+
+/* The current parameters (trained, if training ran), canonical order,
+ * nfloats = mcmg_weights_size's float count, into host memory. */
+mcmg_status mcmg_get_weights(mcmg_handle h, float* out, size_t nfloats);
+
 /* ---- Born-series form (appendix on the Born-series variant; appendix on
  * the discrete Green operator, Eq. discrete_symbol) ----------------------
  *

@@ -73,6 +73,11 @@ class ServerStats(ctypes.Structure):
                 ("inflight_peak", ctypes.c_int), ("ticks", ctypes.c_longlong), ("rebuilds", ctypes.c_longlong)]
 
 
+class Adam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_double), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 _lib = None
 
 EXPORTS = {
@@ -85,6 +90,20 @@ EXPORTS = {
                                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
     "mcmg_stationary": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
+    "mcmg_train_step": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Adam),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "mcmg_train_loss_grad": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]),
+    "mcmg_train_set_trainable": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.c_int]),
+    "mcmg_train_commit": (ctypes.c_int, [ctypes.c_void_p]),
+    "mcmg_weights_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "mcmg_get_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.c_size_t]),
     "mcmg_born_setup": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double]),
     "mcmg_born_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double)]),
@@ -234,6 +253,32 @@ class Handle:
 
     def stationary(self, f, u, tol=1e-6, maxit=500, hist_cap=4096):
         return self._solve(lib().mcmg_stationary, f, u, tol, maxit, hist_cap)
+
+    # ---- training (L_H, Adam, LLPF) ----
+    def weights_size(self):
+        nt, nf = ctypes.c_int(), ctypes.c_size_t()
+        _check(lib().mcmg_weights_size(self.ptr, ctypes.byref(nt), ctypes.byref(nf)))
+        return nt.value, nf.value
+
+    def get_weights(self):
+        """Current parameters as a float32 vector in canonical order."""
+        _, nf = self.weights_size()
+        out = np.empty(nf, dtype=np.float32)
+        _check(lib().mcmg_get_weights(self.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), nf))
+        return out
+
+    def export_blob(self):
+        """The current parameters as a weight blob (same model as the handle's)."""
+        from .weights import build_blob, parse_blob, split_flat
+        head, tens = parse_blob(self._blob)
+        return build_blob(head, split_flat(tens, self.get_weights()))
+
+    def set_trainable(self, mask):
+        m = (ctypes.c_int * len(mask))(*[1 if v else 0 for v in mask])
+        _check(lib().mcmg_train_set_trainable(self.ptr, m, len(mask)))
+
+    def commit(self):
+        _check(lib().mcmg_train_commit(self.ptr))
 
     # ---- Born-series form (periodic operator, discrete Green operator) ----
     def born_setup(self, k0sq=0.0, eps=0.0):
@@ -392,3 +437,34 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _train_args(handles, residuals):
+    if len(handles) != len(residuals) or not handles:
+        raise ValueError("one residual per handle")
+    for H, r in zip(handles, residuals):
+        H._shape_check(r)
+    hs = (ctypes.c_void_p * len(handles))(*[H.ptr.value for H in handles])
+    rs = (ctypes.c_void_p * len(residuals))(*[_ptr(r) for r in residuals])
+    return hs, rs
+
+
+def train_step(handles, residuals, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step on handles[0]'s parameters from L_H over the batch
+    (handles[i], residuals[i]); returns L_H before the update."""
+    hs, rs = _train_args(handles, residuals)
+    loss = ctypes.c_double()
+    opt = Adam(lr, beta1, beta2, eps)
+    _check(lib().mcmg_train_step(hs, len(handles), rs, ctypes.byref(opt), ctypes.byref(loss)))
+    return loss.value
+
+
+def train_loss_grad(handles, residuals):
+    """(L_H, gradient as a float32 vector in canonical order) without an update."""
+    hs, rs = _train_args(handles, residuals)
+    _, nf = handles[0].weights_size()
+    g = np.empty(nf, dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(lib().mcmg_train_loss_grad(hs, len(handles), rs, ctypes.byref(loss),
+                                      g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), nf))
+    return loss.value, g

@@ -6,7 +6,8 @@
 //           - k_I^2 (1 + i gamma_I) u_I
 // with cm_a = 1/(h^2 s_a(I) s_a(I-1/2)), cp_a = 1/(h^2 s_a(I) s_a(I+1/2))
 // (divergence form of the stretched Laplacian; Dirichlet zero outside the
-// extended grid, or periodic wrap-around for the Born form).  PML: gamma = 0;
+// extended grid, or periodic wrap-around for the Born form; the adjoint form
+// applies A^H for the training gradient).  PML: gamma = 0;
 // sponge: s = 1 and gamma = gmax min(1, sum_a g_a[I_a]) from per-axis tables.
 // Per node it streams u (16 B), k^2 (8 B) and the output (16 B); the
 // residual form also reads f (16 B) and emits block partial sums of
@@ -69,7 +70,8 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
       i[1] = (int)(t % n.n[1]); t /= n.n[1];
       i[0] = (int)t;
     }
-    const cplx uc = ld(u, p);
+    cplx uc = ld(u, p);
+    if (A.op.adjoint) uc.im = -uc.im;
     const double kk = k2[p];
     cplx acc = {-kk * uc.re, -kk * uc.im};
     if (A.op.gmax != 0.0) {
@@ -90,17 +92,27 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
       const int ax = (D == 2) ? a : a;
       const cplx m = ld(cms[ax], i[ax]);
       const cplx pc = ld(cps[ax], i[ax]);
+      const cplx d = {m.re + pc.re, m.im + pc.im};
       cplx um = {0.0, 0.0}, up = {0.0, 0.0};
       const long long wrap = (long long)(n.n[ax] - 1) * stride[ax];
       if (i[ax] > 0) um = ld(u, p - stride[ax]);
       else if (A.op.periodic) um = ld(u, p + wrap);
       if (i[ax] < n.n[ax] - 1) up = ld(u, p + stride[ax]);
       else if (A.op.periodic) up = ld(u, p - wrap);
-      const cplx d = {m.re + pc.re, m.im + pc.im};
-      const cplx t0 = cmul(d, uc), t1 = cmul(m, um), t2 = cmul(pc, up);
+      cplx cmw = m, cpw = pc;
+      if (A.op.adjoint) {
+        // row I of A^T: the coupling to I - e_a is A[I-e_a][I] = -cp_a(i - 1),
+        // to I + e_a it is A[I+e_a][I] = -cm_a(i + 1); input conjugated
+        um.im = -um.im;
+        up.im = -up.im;
+        cmw = i[ax] > 0 ? ld(cps[ax], i[ax] - 1) : cplx{0.0, 0.0};
+        cpw = i[ax] < n.n[ax] - 1 ? ld(cms[ax], i[ax] + 1) : cplx{0.0, 0.0};
+      }
+      const cplx t0 = cmul(d, uc), t1 = cmul(cmw, um), t2 = cmul(cpw, up);
       acc.re += t0.re - t1.re - t2.re;
       acc.im += t0.im - t1.im - t2.im;
     }
+    if (A.op.adjoint) acc.im = -acc.im;   // A^H v = conj(A^T conj(v))
     if (f) {
       const cplx fc = ld(f, p);
       acc.re = fc.re - acc.re;

@@ -83,6 +83,7 @@ struct HelmOp {
   double gmax;            // 0: no sponge term
   const double* g[3];     // [n_a] squared normalised distance into the layer
   int periodic = 0;       // 1: neighbours wrap around every axis (Born form)
+  int adjoint = 0;        // 1: apply A^H (conjugate transpose) instead of A
 };
 
 // out = A u (f == nullptr) or out = f - A u; if partial != nullptr the
@@ -319,4 +320,37 @@ struct BornStatsArgs {
 };
 int born_stats_blocks(long long n);
 hipError_t launch_born_stats(const BornStatsArgs& a, int pass, hipStream_t s);
+}  // namespace mcmg
+
+namespace mcmg {
+// ---- Training (weight gradients, adjoint layouts, Adam) --------------------
+// canonical [d0][d1][taps] -> convolution layout [tap][cin][cpad]
+hipError_t launch_repack(const float* w, int d0, int d1, int taps, int transposed, int flip,
+                         float scale, int cin, int cpad, float* out, hipStream_t s);
+// dw (canonical) += scale * gradient of the convolution y = w * x of `mode`
+struct WgArgs {
+  int dim, mode, tx;        // ConvMode; ElemType of x (T_F32 or T_F64)
+  const void* x;            // [in nodes][cin]
+  const float* dy;          // [out nodes][cout]
+  int cin, cout;
+  Dims in, out;
+  float* dw;                // canonical tensor
+  float scale;
+  float* part;              // [nchunk][taps cin cout] partial sums
+  int nchunk;
+  long long chunk;          // output nodes per chunk
+};
+long long wgrad_part_floats(const WgArgs& a);
+hipError_t launch_wgrad(WgArgs a, hipStream_t s);
+hipError_t launch_gelu_fwd(const float* z, float* a, long long n, hipStream_t s);
+hipError_t launch_gelu_bwd(const float* dy, const float* z, float* dz, long long n, hipStream_t s);
+hipError_t launch_mul(float* out, const float* x, const float* y, long long n, float scale,
+                      int acc, hipStream_t s);
+hipError_t launch_axpy(float* out, const float* x, long long n, float scale, hipStream_t s);
+hipError_t launch_c2f(const double* c, float* out, long long n, double scale, hipStream_t s);
+struct AdamArgs {
+  float lr, b1, b2, eps, bc1, bc2;   // bc = 1 - beta^t (bias corrections)
+};
+hipError_t launch_adam(float* th, const float* g, float* m, float* v, long long n,
+                       const AdamArgs& a, hipStream_t s);
 }  // namespace mcmg

@@ -193,6 +193,57 @@ hipError_t Ctx::conv_level(Level& lv, int epi, const float* x, const float* w, c
   return run_mop(op, x, wm, wm2, y, r, feat);
 }
 
+namespace {
+// float32 weights -> the device copy of a matrix-core pack (bf16 with round
+// to nearest even when the form is bf16)
+hipError_t upload_pack(const std::vector<float>& f, void* dst, bool bf) {
+  if (!bf) return hipMemcpy(dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+  std::vector<uint16_t> b(f.size());
+  for (size_t i = 0; i < f.size(); ++i) {
+    uint32_t u;
+    memcpy(&u, &f[i], 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    b[i] = (uint16_t)(u >> 16);
+  }
+  return hipMemcpy(dst, b.data(), b.size() * 2, hipMemcpyHostToDevice);
+}
+}  // namespace
+
+// Re-pack changed weights (host_w) into the existing matrix-core buffers and
+// level-1 sweep weights, keeping every plan and tile.
+mcmg_status Ctx::refresh_packed() {
+  const bool bf = precision == MCMG_BF16;
+  const int KV = bf ? 8 : 1;
+  auto tensor = [&](int kind, int level, int step) -> const std::vector<float>* {
+    for (const HostTensor& t : host_w)
+      if (t.kind == kind && t.level == level && t.step == step) return &t.w;
+    return nullptr;
+  };
+  auto put = [&](const std::vector<float>* w, const MOp& op, void* dst) -> mcmg_status {
+    if (!dst) return MCMG_OK;
+    if (!w) return fail(MCMG_E_WEIGHTS, "missing tensor");
+    MOp proto = op;
+    if (upload_pack(pack_gemm(*w, dim, proto, KV), dst, bf) != hipSuccess)
+      return fail(MCMG_E_HIP, "weight re-pack");
+    return MCMG_OK;
+  };
+  mcmg_status st;
+  for (int l = 0; l < L; ++l) {
+    Level& lv = lev[l];
+    const int lvl = l + 1;
+    if (lv.m_W) {
+      if ((st = put(tensor(4, lvl, 0), lv.op_resid, lv.m_W)) != MCMG_OK) return st;
+      if ((st = put(tensor(5, lvl, 0), lv.op_resid, lv.m_KA)) != MCMG_OK) return st;
+      if ((st = put(tensor(6, lvl, 0), lv.op_resid, lv.m_KS)) != MCMG_OK) return st;
+      for (size_t i = 0; i < lv.m_sm.size(); ++i)
+        if ((st = put(tensor(7, lvl, (int)i + 1), lv.op_resid, lv.m_sm[i])) != MCMG_OK) return st;
+    }
+    if (lv.m_R && (st = put(tensor(9, lvl, 0), lv.op_R, lv.m_R)) != MCMG_OK) return st;
+    if (lv.m_P && (st = put(tensor(10, lvl, 0), lv.op_P, lv.m_P)) != MCMG_OK) return st;
+  }
+  return refresh_level1();
+}
+
 mcmg_status Ctx::plan_mfma() {
   const int bf = precision == MCMG_BF16 ? 1 : 0;
   const int KV = bf ? 8 : 1;

@@ -56,6 +56,7 @@ Ctx::~Ctx() {
   for (Slot& sl : slots) if (sl.chunk) (void)hipFree(sl.chunk);
   for (void* p : allocs) (void)hipFree(p);
   if (host_scal) (void)hipHostFree(host_scal);
+  delete train;
 }
 
 }  // namespace mcmg
@@ -347,7 +348,9 @@ hipError_t Ctx::level1(Level& lv, int var, int step) {
   return e;
 }
 
-mcmg_status Ctx::plan_level1() {
+mcmg_status Ctx::refresh_level1() { return plan_level1(true); }
+
+mcmg_status Ctx::plan_level1(bool refresh) {
   for (int l = 0; l < L; ++l) {
     Level& lv = lev[l];
     if (lv.C != 2) continue;
@@ -375,11 +378,13 @@ mcmg_status Ctx::plan_level1() {
       if (!ws) return fail(MCMG_E_WEIGHTS, "missing smoother tensor");
       fill(w.Wsm, *ws);
     }
-    lv.e_alt = (float*)alloc((size_t)lv.dims.total * 2 * sizeof(float));
-    if (!lv.e_alt) return fail(MCMG_E_OOM, "level allocation failed");
-    lv.l1w_dev.assign(lv.l1w.size(), nullptr);
+    if (!refresh) {
+      lv.e_alt = (float*)alloc((size_t)lv.dims.total * 2 * sizeof(float));
+      if (!lv.e_alt) return fail(MCMG_E_OOM, "level allocation failed");
+      lv.l1w_dev.assign(lv.l1w.size(), nullptr);
+    }
     for (size_t i = 0; i < lv.l1w.size(); ++i) {
-      lv.l1w_dev[i] = (L1Weights*)alloc(sizeof(L1Weights));
+      if (!refresh) lv.l1w_dev[i] = (L1Weights*)alloc(sizeof(L1Weights));
       if (!lv.l1w_dev[i]) return fail(MCMG_E_OOM, "weight allocation failed");
       if (hipMemcpy(lv.l1w_dev[i], &lv.l1w[i], sizeof(L1Weights), hipMemcpyHostToDevice) != hipSuccess)
         return fail(MCMG_E_HIP, "weight upload failed");

@@ -124,6 +124,33 @@ struct BornState {
   int nstats = 0;
 };
 
+// Training state (train.cpp): parameters, gradients and Adam moments in the
+// canonical blob layout, adjoint-layout copies of every tensor, and the tape
+// of one forward pass.
+struct TTensor {
+  int kind = 0, level = 0, step = 0, d0 = 0, d1 = 0, mode = 0;
+  size_t off = 0, len = 0;          // in the canonical flat vectors
+  bool train = true;                // false: frozen (LLPF)
+  float** fwd = nullptr;            // the handle's forward-layout pointer
+  float* adj = nullptr;             // adjoint layout (nullptr: not needed)
+  int adj_cin = 0, adj_cout = 0;
+};
+struct TrainState {
+  std::vector<TTensor> ts;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  size_t n = 0;
+  int t = 0;                                    // Adam step count
+  float* z_lift = nullptr;                      // setup pre-activations
+  std::vector<float*> z_s, z_a;
+  std::vector<std::vector<float*>> te, tt, tu;  // tape per level and step: e before, t, u
+  std::vector<float*> rr, edown;                // restriction input, e after the down steps
+  std::vector<float*> gde, gdr, gda, gds, t1, t2, t3;
+  float *z2 = nullptr, *dz2 = nullptr, *rin32 = nullptr;
+  double *wres = nullptr, *ahw = nullptr;
+  float* part = nullptr;
+  size_t part_cap = 0;
+};
+
 struct Ctx {
   int dim = 2;
   int nint[3] = {1, 1, 1};
@@ -207,10 +234,22 @@ struct Ctx {
   hipError_t vcycle(const void* rin, int tin, void* zout, int tout);
   hipError_t smooth_step(Level& lv, int i, bool first);
   hipError_t level1(Level& lv, int var, int step);   // fused C = 2 sweep
-  mcmg_status plan_level1();
+  mcmg_status plan_level1(bool refresh = false);
+  mcmg_status refresh_level1();                 // re-derive level-1 sweep weights
+  mcmg_status refresh_packed();                 // re-pack matrix-core weights (+ level 1)
   hipError_t run_setup();
   HelmOp helm() const;
   hipError_t helm_timed(int tin, const void* u, const double* f, double* out, double* partial);
+
+  // training (train.cpp)
+  TrainState* train = nullptr;
+  mcmg_status train_init();
+  hipError_t train_sync_weights();             // canonical -> forward and adjoint layouts
+  hipError_t train_forward(const double* rin);
+  hipError_t train_backward();
+  hipError_t wgrad(int mode, int tx, const void* x, const Dims& in, int cin, const float* dy,
+                   const Dims& out, int cout, const TTensor& t, float scale);
+  mcmg_status repack_inference();              // MFMA packs, level-1 sweep weights, features
 
   // Born series (born.cpp)
   BornState born;
