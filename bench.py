@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--born-iters", type=int, default=20,
                     help="Born-series steps per method in the Born leg (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=50,
+                    help="Adam steps of the training leg (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=3)
     return ap.parse_args()
@@ -433,6 +435,47 @@ def born_leg(cfg, c, omega, h, f, blob, precision, iters):
     return out
 
 
+def train_leg(steps, batch=2, seed=7):
+    """Training throughput on the small workload's shape (64^2 interior, 8-cell
+    PML, 3 levels 2/8/16, nu 2/2): Adam steps on L_H (Eq. loss_fun) with
+    N(0, I) residuals, `batch` media per step (the bump medium with seeded
+    +-10 % perturbations), FP32 VALU forward and reverse pass."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_30495_amd import Handle, train_step
+    cfg = synth.CONFIGS["bump64"]
+    tens = synth.make_weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, 0)
+    blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
+    h = 1.0 / cfg.n
+    rng = np.random.Generator(np.random.PCG64(seed))
+    hs = []
+    for i in range(batch):
+        c = synth.medium_bump(cfg.n, cfg.dim) * rng.uniform(0.9, 1.1, size=(cfg.n,) * cfg.dim)
+        hs.append(Handle(c, synth.omega_for_ppw(c, cfg.ppw, h), h, cfg.npml, blob))
+    shape = hs[0].ext_shape
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+
+    def draw():
+        return [torch.complex(torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64),
+                              torch.randn(shape, generator=gen, device="cuda", dtype=torch.float64))
+                for _ in hs]
+
+    train_step(hs, draw(), lr=1e-2)    # warm-up (allocates the training state)
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        losses.append(train_step(hs, draw(), lr=1e-2))
+    el = time.perf_counter() - t0
+    for H in hs:
+        H.close()
+    return {"workload": "bump64 shape, media with seeded +-10% perturbations, random-init start",
+            "batch": batch, "steps": steps, "steps_per_s": round(steps / el, 2),
+            "samples_per_s": round(steps * batch / el, 2), "ms_per_step": round(el / steps * 1e3, 3),
+            "loss_first": round(losses[0], 4), "loss_last": round(losses[-1], 4)}
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -496,6 +539,9 @@ def main():
     if a.born_iters > 0 and cfg.dim == 2:
         line["born"] = born_leg(cfg, c, omega, h, f, blob, a.precision, a.born_iters)
         progress("Born leg done")
+    if a.train_steps > 0:
+        line["train"] = train_leg(a.train_steps)
+        progress("training leg done")
     if cmp_leg is not None:
         line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
                            "ms_per_step": round(cmp_leg["ms_per_step"], 4),
