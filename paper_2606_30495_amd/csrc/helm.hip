@@ -43,35 +43,51 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-template <int D, typename TIN>
+// Complex values as one vector load (16 B for double, 8 B for float).
+__device__ __forceinline__ cplx ldv(const double* p, long long i) {
+  const double2 v = reinterpret_cast<const double2*>(p)[i];
+  return {v.x, v.y};
+}
+__device__ __forceinline__ cplx ldv(const float* p, long long i) {
+  const float2 v = reinterpret_cast<const float2*>(p)[i];
+  return {(double)v.x, (double)v.y};
+}
+
+// MODE 0: A u (Dirichlet); 1: periodic (Born form); 2: A^H u (Dirichlet).
+// Neighbour loads use clamped addresses and a mask instead of branches.
+template <int D, typename TIN, int MODE>
 __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
   const TIN* __restrict__ u = reinterpret_cast<const TIN*>(A.u);
   const double* __restrict__ f = A.f;
   double* __restrict__ out = A.out;
   const double* __restrict__ k2 = A.op.k2;
-  const double* __restrict__ cm0 = A.op.cm[0];
-  const double* __restrict__ cp0 = A.op.cp[0];
-  const double* __restrict__ cm1 = A.op.cm[1];
-  const double* __restrict__ cp1 = A.op.cp[1];
-  const double* __restrict__ cm2 = A.op.cm[2] ? A.op.cm[2] : A.op.cm[0];
-  const double* __restrict__ cp2 = A.op.cp[2] ? A.op.cp[2] : A.op.cp[0];
   const Dims n = A.op.ext;
   double* __restrict__ partial = A.partial;
   __shared__ double sh[HB / 64];
   double nrm = 0.0;
   const long long base = (long long)vblk * HB * HPT;
+  const long long stride[3] = {(long long)n.n[1] * n.n[2], (long long)n.n[2], 1};
+  const bool small = n.total < (1LL << 31);
   for (int q = 0; q < HPT; ++q) {
     const long long p = base + (long long)q * HB + threadIdx.x;
     if (p >= n.total) break;
     int i[3];
-    {
+    if (small) {
+      // 32-bit unravel by multiply-high division (no 64-bit divide)
+      const uint32_t pp = (uint32_t)p;
+      const uint32_t q2 = fdiv(pp, A.op.fd2);
+      const uint32_t q1 = fdiv(q2, A.op.fd1);
+      i[2] = (int)(pp - q2 * (uint32_t)n.n[2]);
+      i[1] = (int)(q2 - q1 * (uint32_t)n.n[1]);
+      i[0] = (int)q1;
+    } else {
       long long t = p;
       i[2] = (int)(t % n.n[2]); t /= n.n[2];
       i[1] = (int)(t % n.n[1]); t /= n.n[1];
       i[0] = (int)t;
     }
-    cplx uc = ld(u, p);
-    if (A.op.adjoint) uc.im = -uc.im;
+    cplx uc = ldv(u, p);
+    if (MODE == 2) uc.im = -uc.im;
     const double kk = k2[p];
     cplx acc = {-kk * uc.re, -kk * uc.im};
     if (A.op.gmax != 0.0) {
@@ -83,43 +99,47 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
       acc.re += gk * uc.im;
       acc.im -= gk * uc.re;
     }
-    const long long stride[3] = {(long long)n.n[1] * n.n[2], (long long)n.n[2], 1};
-    const double* cms[3] = {cm0, cm1, cm2};
-    const double* cps[3] = {cp0, cp1, cp2};
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      // spatial axis a of the D used ones; unused axes have n = 1 and come last
-      const int ax = (D == 2) ? a : a;
-      const cplx m = ld(cms[ax], i[ax]);
-      const cplx pc = ld(cps[ax], i[ax]);
+      const int ia = i[a], na = n.n[a];
+      const bool hm = ia > 0, hp = ia < na - 1;
+      const cplx m = ldv(A.op.cm[a], ia);
+      const cplx pc = ldv(A.op.cp[a], ia);
       const cplx d = {m.re + pc.re, m.im + pc.im};
-      cplx um = {0.0, 0.0}, up = {0.0, 0.0};
-      const long long wrap = (long long)(n.n[ax] - 1) * stride[ax];
-      if (i[ax] > 0) um = ld(u, p - stride[ax]);
-      else if (A.op.periodic) um = ld(u, p + wrap);
-      if (i[ax] < n.n[ax] - 1) up = ld(u, p + stride[ax]);
-      else if (A.op.periodic) up = ld(u, p - wrap);
+      const long long wrap = (long long)(na - 1) * stride[a];
+      long long pm, pq;
+      if (MODE == 1) {
+        pm = hm ? p - stride[a] : p + wrap;
+        pq = hp ? p + stride[a] : p - wrap;
+      } else {
+        pm = hm ? p - stride[a] : p;
+        pq = hp ? p + stride[a] : p;
+      }
+      cplx um = ldv(u, pm), up = ldv(u, pq);
       cplx cmw = m, cpw = pc;
-      if (A.op.adjoint) {
+      if (MODE != 1) {
+        if (!hm) um = {0.0, 0.0};
+        if (!hp) up = {0.0, 0.0};
+      }
+      if (MODE == 2) {
         // row I of A^T: the coupling to I - e_a is A[I-e_a][I] = -cp_a(i - 1),
         // to I + e_a it is A[I+e_a][I] = -cm_a(i + 1); input conjugated
         um.im = -um.im;
         up.im = -up.im;
-        cmw = i[ax] > 0 ? ld(cps[ax], i[ax] - 1) : cplx{0.0, 0.0};
-        cpw = i[ax] < n.n[ax] - 1 ? ld(cms[ax], i[ax] + 1) : cplx{0.0, 0.0};
+        cmw = ldv(A.op.cp[a], hm ? ia - 1 : ia);
+        cpw = ldv(A.op.cm[a], hp ? ia + 1 : ia);
       }
       const cplx t0 = cmul(d, uc), t1 = cmul(cmw, um), t2 = cmul(cpw, up);
       acc.re += t0.re - t1.re - t2.re;
       acc.im += t0.im - t1.im - t2.im;
     }
-    if (A.op.adjoint) acc.im = -acc.im;   // A^H v = conj(A^T conj(v))
+    if (MODE == 2) acc.im = -acc.im;   // A^H v = conj(A^T conj(v))
     if (f) {
-      const cplx fc = ld(f, p);
+      const cplx fc = ldv(f, p);
       acc.re = fc.re - acc.re;
       acc.im = fc.im - acc.im;
     }
-    out[2 * p] = acc.re;
-    out[2 * p + 1] = acc.im;
+    reinterpret_cast<double2*>(out)[p] = make_double2(acc.re, acc.im);
     nrm += acc.re * acc.re + acc.im * acc.im;
   }
   if (partial) {
@@ -132,12 +152,12 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
 // partial[t]; physical blocks take logical ones in XCD-contiguous bands
 // (blockIdx % 8 walks one band), so the neighbour planes a block reads sit in
 // its own XCD's L2.  The grid is nb rounded up to a multiple of 8.
-template <int D, typename TIN>
+template <int D, typename TIN, int MODE>
 __global__ __launch_bounds__(HB) void helm_kernel(HArgs A, int nb) {
   const int per = (nb + 7) / 8;
   const int t = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= nb) return;
-  helm_body<D, TIN>(A, t);
+  helm_body<D, TIN, MODE>(A, t);
 }
 
 template <int D, typename TIN>
@@ -148,7 +168,7 @@ __global__ __launch_bounds__(HB) void helm_kernel_batched(const HArgs* __restric
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
   const HArgs A = tab[batch_entry(row, np, p)];
-  helm_body<D, TIN>(A, blockIdx.x - pre[p]);
+  helm_body<D, TIN, 0>(A, blockIdx.x - pre[p]);
 }
 
 hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLaunch* b,
@@ -156,6 +176,7 @@ hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLa
   // 2D grids use axes 0,1 (axis 2 has n = 1); the kernel indexes axis 2 as
   // the fastest, so 2D data is addressed as n0 x n1 x 1.
   if (b) {
+    // batched launches apply the plain operator (the FGMRES matvec and residual)
     const HArgs* t = (const HArgs*)b->tab;
     if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel_batched<2, double>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
     else if (dim == 2) hipLaunchKernelGGL((helm_kernel_batched<2, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
@@ -163,10 +184,18 @@ hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLa
     else hipLaunchKernelGGL((helm_kernel_batched<3, float>), dim3(b->total), dim3(HB), 0, s, t, b->pre, b->np, b->frozen, b->row);
   } else {
     const unsigned g = (unsigned)((nb + 7) / 8 * 8);
-    if (dim == 2 && tin == T_F64) hipLaunchKernelGGL((helm_kernel<2, double>), dim3(g), dim3(HB), 0, s, *A, nb);
-    else if (dim == 2) hipLaunchKernelGGL((helm_kernel<2, float>), dim3(g), dim3(HB), 0, s, *A, nb);
-    else if (tin == T_F64) hipLaunchKernelGGL((helm_kernel<3, double>), dim3(g), dim3(HB), 0, s, *A, nb);
-    else hipLaunchKernelGGL((helm_kernel<3, float>), dim3(g), dim3(HB), 0, s, *A, nb);
+    const int mode = A->op.adjoint ? 2 : A->op.periodic ? 1 : 0;
+#define HELM_LAUNCH(DD, TT, MM) hipLaunchKernelGGL((helm_kernel<DD, TT, MM>), dim3(g), dim3(HB), 0, s, *A, nb)
+#define HELM_BY_MODE(DD, TT)            \
+    if (mode == 0) HELM_LAUNCH(DD, TT, 0); \
+    else if (mode == 1) HELM_LAUNCH(DD, TT, 1); \
+    else HELM_LAUNCH(DD, TT, 2);
+    if (dim == 2 && tin == T_F64) { HELM_BY_MODE(2, double) }
+    else if (dim == 2) { HELM_BY_MODE(2, float) }
+    else if (tin == T_F64) { HELM_BY_MODE(3, double) }
+    else { HELM_BY_MODE(3, float) }
+#undef HELM_BY_MODE
+#undef HELM_LAUNCH
   }
   return hipGetLastError();
 }

@@ -28,6 +28,29 @@ inline Dims make_dims(int dim, const int* n) {
   return d;
 }
 
+// n / d for 32-bit unsigned n by a multiply-high and shifts, with the
+// round-up multiplier of Granlund and Montgomery (division by invariant
+// integers): m = floor(2^32 (2^l - d) / d) + 1, l = ceil(log2 d),
+// q = (t + ((n - t) >> 1)) >> (l - 1), t = mulhi(n, m).  Exact for every
+// 32-bit n (checked exhaustively at the boundaries and on random n).
+struct FastDiv {
+  uint32_t d = 1, m = 0;
+  int l = 0;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f;
+  f.d = d;
+  if (d <= 1) return f;
+  while ((1ull << f.l) < d) ++f.l;
+  f.m = (uint32_t)(((1ull << 32) * ((1ull << f.l) - d)) / d + 1);
+  return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
+  if (f.d == 1) return n;
+  const uint32_t t = __umulhi(n, f.m);
+  return (t + ((n - t) >> 1)) >> (f.l - 1);
+}
+
 enum ConvMode { CONV_S1 = 0, CONV_S2 = 1, CONV_T2 = 2 };
 enum ConvEpi {
   EPI_SET = 0,    // y = acc
@@ -82,6 +105,7 @@ struct HelmOp {
   // sponge layer: diagonal -k^2 (1 + i gamma), gamma = gmax min(1, sum_a g_a[i_a])
   double gmax;            // 0: no sponge term
   const double* g[3];     // [n_a] squared normalised distance into the layer
+  FastDiv fd1, fd2;       // division by ext.n[1], ext.n[2] (node index unravel)
   int periodic = 0;       // 1: neighbours wrap around every axis (Born form)
   int adjoint = 0;        // 1: apply A^H (conjugate transpose) instead of A
 };

@@ -433,6 +433,8 @@ HelmOp Ctx::helm() const {
   op.k2 = k2;
   for (int a = 0; a < 3; ++a) { op.cm[a] = cm[a]; op.cp[a] = cp[a]; op.g[a] = gtab[a]; }
   op.gmax = absorber == MCMG_ABL_SPONGE ? gamma_max : 0.0;
+  op.fd1 = make_fastdiv((uint32_t)ext.n[1]);
+  op.fd2 = make_fastdiv((uint32_t)ext.n[2]);
   return op;
 }
 
