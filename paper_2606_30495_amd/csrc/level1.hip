@@ -318,6 +318,33 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
       }
     }
   };
+  // as conv2 for two weight sets X (into c0, c1) and Y (into d0, d1) that read
+  // each staged value once; every accumulator sums its taps in conv2's order
+  auto conv2pair = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
+                       const float* Xw, const float* Yw, const int* base, float* c0, float* c1,
+                       float* d0, float* d1, auto npts) {
+    constexpr int NP = decltype(npts)::value;
+#pragma unroll 1
+    for (int dz = 0; dz < 3; ++dz) {
+      const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
+      const float* w = Xw + dz * 9;
+      const float* y = Yw + dz * 9;
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
+        const float a00 = w[t], a01 = w[27 + t], a10 = w[54 + t], a11 = w[81 + t];
+        const float b00 = y[t], b01 = y[27 + t], b10 = y[54 + t], b11 = y[81 + t];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const float2 v = P[base[k] + to];
+          c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
+          c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+          d0[k] = fmaf(b00, v.x, fmaf(b01, v.y, d0[k]));
+          d1[k] = fmaf(b10, v.x, fmaf(b11, v.y, d1[k]));
+        }
+      }
+    }
+  };
   // t plane q on the t box (halo 2): t = r - W*e - a (.) (KA*e); FIRST: t = r
   auto make_t = [&](int q) {
     float2 rv[PT], av[PT];
@@ -336,10 +363,9 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
     float w0[PT], w1[PT], k0[PT], k1[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
-    if (VAR != L1_FIRST) {
-      conv2(se, NER, NE, q, EX, &wp->W[0][0][0], eb, w0, w1, std::integral_constant<int, PT>());
-      conv2(se, NER, NE, q, EX, &wp->KA[0][0][0], eb, k0, k1, std::integral_constant<int, PT>());
-    }
+    if (VAR != L1_FIRST)
+      conv2pair(se, NER, NE, q, EX, &wp->W[0][0][0], &wp->KA[0][0][0], eb, w0, w1, k0, k1,
+                std::integral_constant<int, PT>());
     float2* dst = st + ring(q, 3) * NT;
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
@@ -422,8 +448,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
         float w0[PO], w1[PO], k0[PO], k1[PO];
 #pragma unroll
         for (int j = 0; j < PO; ++j) w0[j] = w1[j] = k0[j] = k1[j] = 0.f;
-        conv2(se, NER, NE, z, EX, &wp->W[0][0][0], eb, w0, w1, std::integral_constant<int, PO>());
-        conv2(se, NER, NE, z, EX, &wp->KA[0][0][0], eb, k0, k1, std::integral_constant<int, PO>());
+        conv2pair(se, NER, NE, z, EX, &wp->W[0][0][0], &wp->KA[0][0][0], eb, w0, w1, k0, k1,
+                  std::integral_constant<int, PO>());
 #pragma unroll
         for (int j = 0; j < PO; ++j) {
           if (!ok[j]) continue;
