@@ -45,7 +45,15 @@ __device__ __forceinline__ void conv_body(const DArgs& A, const int vblk) {
   if (p >= out.total) return;
   const int chunk = blockIdx.y;
   int o[3];
-  {
+  if (out.total < (1LL << 31)) {
+    // 32-bit unravel by multiply-high division (no 64-bit divide)
+    const uint32_t pp = (uint32_t)p;
+    const uint32_t q2 = fdiv(pp, A.fo2);
+    const uint32_t q1 = fdiv(q2, A.fo1);
+    o[2] = (int)(pp - q2 * (uint32_t)out.n[2]);
+    o[1] = (int)(q2 - q1 * (uint32_t)out.n[1]);
+    o[0] = (int)q1;
+  } else {
     long long q = p;
     o[2] = (int)(q % out.n[2]); q /= out.n[2];
     o[1] = (int)(q % out.n[1]); q /= out.n[1];
@@ -320,6 +328,8 @@ DArgs conv_args(const ConvLaunch& a, int* nblk) {
   DArgs A;
   A.x = a.x; A.w = a.w; A.w2 = a.w2; A.y = a.y; A.r = a.r; A.feat = a.feat;
   A.cin = a.cin; A.cout = a.cout; A.cpad = a.cpad; A.in = a.in; A.out = a.out;
+  A.fo1 = make_fastdiv((uint32_t)a.out.n[1]);
+  A.fo2 = make_fastdiv((uint32_t)a.out.n[2]);
   if (c22z_ok(a) && (a.tin == T_F64 || a.tin == T_F32) && (a.tout == T_F32 || a.tout == T_F64) &&
       !(a.tin == T_F64 && a.tout == T_F64)) {
     int tx, ty, tz;

@@ -280,6 +280,7 @@ struct DArgs {
   const float* feat;
   int cin, cout, cpad;
   Dims in, out;
+  FastDiv fo1, fo2;      // division by out.n[1], out.n[2]
 };
 DArgs conv_args(const ConvLaunch& a, int* nblk);
 hipError_t launch_conv_batched(const ConvLaunch& proto, const BatchLaunch& b, hipStream_t s);
@@ -363,6 +364,7 @@ struct WgArgs {
   float* part;              // [nchunk][taps cin cout] partial sums
   int nchunk;
   long long chunk;          // output nodes per chunk
+  FastDiv fo1, fo2;         // division by out.n[1], out.n[2]
 };
 long long wgrad_part_floats(const WgArgs& a);
 hipError_t launch_wgrad(WgArgs a, hipStream_t s);

@@ -166,6 +166,8 @@ hipError_t Ctx::wgrad(int mode, int tx, const void* x, const Dims& in, int cin, 
   WgArgs a{};
   a.dim = dim; a.mode = mode; a.tx = tx; a.x = x; a.dy = dy; a.cin = cin; a.cout = cout;
   a.in = in; a.out = out; a.dw = T->grad + t.off; a.scale = scale; a.part = T->part;
+  a.fo1 = make_fastdiv((uint32_t)out.n[1]);
+  a.fo2 = make_fastdiv((uint32_t)out.n[2]);
   a.chunk = std::max<long long>(256, (out.total + 63) / 64);
   a.nchunk = (int)((out.total + a.chunk - 1) / a.chunk);
   if ((size_t)wgrad_part_floats(a) > T->part_cap) return hipErrorInvalidValue;

@@ -65,12 +65,22 @@ __global__ __launch_bounds__(TB) void wgrad_partial(WgArgs A) {
   const long long p0 = (long long)blockIdx.y * A.chunk;
   const long long p1 = p0 + A.chunk < A.out.total ? p0 + A.chunk : A.out.total;
   float acc = 0.f;
+  const bool small = A.out.total < (1LL << 31);
   for (long long p = p0; p < p1; ++p) {
-    long long q = p;
     int o[3];
-    o[2] = (int)(q % A.out.n[2]); q /= A.out.n[2];
-    o[1] = (int)(q % A.out.n[1]); q /= A.out.n[1];
-    o[0] = (int)q;
+    if (small) {
+      const uint32_t pp = (uint32_t)p;
+      const uint32_t q2 = fdiv(pp, A.fo2);
+      const uint32_t q1 = fdiv(q2, A.fo1);
+      o[2] = (int)(pp - q2 * (uint32_t)A.out.n[2]);
+      o[1] = (int)(q2 - q1 * (uint32_t)A.out.n[1]);
+      o[0] = (int)q1;
+    } else {
+      long long q = p;
+      o[2] = (int)(q % A.out.n[2]); q /= A.out.n[2];
+      o[1] = (int)(q % A.out.n[1]); q /= A.out.n[1];
+      o[0] = (int)q;
+    }
     int ii[3];
     bool ok = true;
 #pragma unroll
