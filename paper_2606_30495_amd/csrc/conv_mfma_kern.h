@@ -18,6 +18,13 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16;
 
+// Direct global-to-LDS copy of 16 bytes per lane: lane l of the wave writes
+// lds_wave + 16 l (lds_wave must be the same in every lane); inactive lanes
+// write nothing.  Completion is counted by vmcnt of the issuing wave.
+__device__ __forceinline__ void lds_copy16(const void* g, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
+}
+
 __device__ __forceinline__ u16 f2bf(float f) {
   unsigned int u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
@@ -93,41 +100,38 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   else { sx = x0; sy = y0; sz = z0; }
   if (D == 2) sz = 0;
 
-  // weight chunk [s0, s0 + ks): rows q in [4 s0, 4 (s0 + ks)), columns [col0, col0 + 16 NTW)
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+
+  // Weight chunk [s0, s0 + ks): rows q in [4 s0, 4 (s0 + ks)), columns
+  // [col0, col0 + 16 NTW), laid out in LDS as [a][4 ks rows][BROW] so that
+  // 16-byte vector idx of the chunk sits at byte 16 idx.  A wave's 64
+  // consecutive vectors are then one contiguous 1 KB run, which the direct
+  // global-to-LDS load writes (lane l at base + 16 l) with no registers and
+  // no wait in the issuing wave; the wave waits for its own copies (vmcnt)
+  // before the barrier that publishes the chunk.
   auto wsrc = [&](int s0, int ks, int idx) {
     const int nrow = 4 * ks;
     const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
     const int row = rem / V16, vv = rem % V16;
-    return reinterpret_cast<const uint4*>(reinterpret_cast<const unsigned char*>(a ? wB : wA) +
-                                          (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES +
-                                          (size_t)vv * 16);
+    return reinterpret_cast<const unsigned char*>(a ? wB : wA) +
+           (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)vv * 16;
   };
-  auto wdst = [&](int ks, int idx) {
-    const int nrow = 4 * ks;
-    const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
-    const int row = rem / V16, vv = rem % V16;
-    return reinterpret_cast<uint4*>(bsm + (((size_t)a * 4 * kchunk + row) * BROW) * ES + (size_t)vv * 16);
-  };
-  // The first weight chunk is fetched together with the input tile when it
-  // fits in WB vectors per thread (40 KB per block): one memory latency for
-  // both instead of one per batch.
-  constexpr int WB = 10;
-  const int ks0 = nsteps < kchunk ? nsteps : kchunk;
-  const int wtot0 = NACC * 4 * ks0 * V16;
-  const bool wpre = wtot0 <= 256 * WB;
-  uint4 wv[WB];
-  if (wpre) {
-#pragma unroll
-    for (int k = 0; k < WB; ++k) {
-      const int idx = threadIdx.x + k * 256;
-      if (idx < wtot0) wv[k] = *wsrc(0, ks0, idx);
+  auto wfetch = [&](int s0, int ks) {
+    const int total = NACC * 4 * ks * V16;
+    for (int base = wave * 64; base < total; base += 256) {
+      const int idx = base + lane;
+      if (idx < total) lds_copy16(wsrc(s0, ks, idx), bsm + (size_t)__builtin_amdgcn_readfirstlane(base) * 16);
     }
-  }
+  };
+  const int ks0 = nsteps < kchunk ? nsteps : kchunk;
+  wfetch(0, ks0);
 
   // ---- stage the input tile: loads are issued in batches of SB per thread
   // before any LDS store, so a block waits for one memory latency per batch
+  // (small tiles, used on small grids, take the whole tile in one batch)
   {
-    constexpr int SB = 8;
+    constexpr int SB = (RPW * MT * NTW <= 2) ? 12 : 8;
     const bool vec4 = (cin % 4) == 0;
     const int ng = cinp / 4;
     const int total = G::NODES * ng;
@@ -159,8 +163,11 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
         if (idx >= total) continue;
         const int node = idx / ng, c = (idx % ng) * 4;
         if constexpr (BF) {
-          u16* s = reinterpret_cast<u16*>(smem) + (size_t)node * stride + c;
-          s[0] = f2bf(v[k].x); s[1] = f2bf(v[k].y); s[2] = f2bf(v[k].z); s[3] = f2bf(v[k].w);
+          // four bf16 values in one 8-byte store (node rows are 16-byte
+          // aligned, c is a multiple of 4)
+          const unsigned lo = (unsigned)f2bf(v[k].x) | ((unsigned)f2bf(v[k].y) << 16);
+          const unsigned hi = (unsigned)f2bf(v[k].z) | ((unsigned)f2bf(v[k].w) << 16);
+          *reinterpret_cast<uint2*>(reinterpret_cast<u16*>(smem) + (size_t)node * stride + c) = make_uint2(lo, hi);
         } else {
           float* s = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
           s[0] = v[k].x; s[1] = v[k].y; s[2] = v[k].z; s[3] = v[k].w;
@@ -168,16 +175,8 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
       }
     }
   }
-  if (wpre) {
-#pragma unroll
-    for (int k = 0; k < WB; ++k) {
-      const int idx = threadIdx.x + k * 256;
-      if (idx < wtot0) *wdst(ks0, idx) = wv[k];
-    }
-  }
-
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lg = lane >> 4;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's weight copies are in LDS
+  __syncthreads();                                   // tile and first weight chunk published
 
   // output offsets and epilogue operands of every accumulator element; for
   // small tiles the operands are fetched here, so their latency overlaps
@@ -237,25 +236,12 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   const int KS = kchunk;
   for (int s0 = 0; s0 < nsteps; s0 += KS) {
     const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
-    if (s0 > 0 || !wpre) {
-      __syncthreads();   // previous chunk consumed (and input tile staged)
-      constexpr int SB = 8;
-      const int total = NACC * 4 * ks * V16;
-      for (int base = threadIdx.x; base < total; base += 256 * SB) {
-        uint4 v[SB];
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int idx = base + k * 256;
-          if (idx < total) v[k] = *wsrc(s0, ks, idx);
-        }
-#pragma unroll
-        for (int k = 0; k < SB; ++k) {
-          const int idx = base + k * 256;
-          if (idx < total) *wdst(ks, idx) = v[k];
-        }
-      }
+    if (s0 > 0) {
+      __syncthreads();   // previous chunk consumed
+      wfetch(s0, ks);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
     }
-    __syncthreads();
 #pragma unroll 2
     for (int ss = 0; ss < ks; ++ss) {
       const int s = s0 + ss;
@@ -270,7 +256,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
       for (int a = 0; a < NACC; ++a)
 #pragma unroll
         for (int t = 0; t < NTW; ++t) {
-          const size_t o = ((size_t)a * 4 * KS + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
+          const size_t o = ((size_t)a * 4 * ks + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
           if constexpr (BF) bf[a][t] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(bsm) + o);
           else bf[a][t] = reinterpret_cast<const float*>(bsm)[o];
         }
