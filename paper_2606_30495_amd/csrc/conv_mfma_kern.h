@@ -234,6 +234,43 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
 
   const int cpv = cinp / KV;
   const int KS = kchunk;
+  // LDS element offset of tap (0, 0, 0) for each (row, m) of this lane: the
+  // staged node of tap (dz, dy, dx) is this base plus (dz HY + dy) HX + dx
+  // in every mode
+  int abase[RPW][MT];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int rho = wave + 4 * i;
+    const int wy = rho % G::TY, wz = rho / G::TY;
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int ox = m * 16 + li;   // output x inside the tile
+      const int f = (MODE == CONV_S2) ? 2 : 1;
+      abase[i][m] = ((f * wz * G::HY + f * wy) * G::HX + f * ox) * stride;
+    }
+  }
+  // Small tiles (used on small grids, where a block's latency is the
+  // launch's) read the fragments of step ss + 1 before the products of step
+  // ss are issued (two register sets), so LDS latency overlaps the matrix
+  // cores; larger tiles keep one set, for occupancy.  Every accumulator
+  // takes the steps in order.  Steps are loaded in order, so the pair walk
+  // advances once per load.
+  PairWalk pw;
+  pw.init(lg, cpv, npairs);
+  typedef typename std::conditional<BF, bf16x8, float>::type Frag;
+  auto mma = [&](const Frag (&bf)[NACC][NTW], const Frag (&af)[RPW][MT]) {
+#pragma unroll
+    for (int i = 0; i < RPW; ++i)
+#pragma unroll
+      for (int m = 0; m < MT; ++m)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t)
+#pragma unroll
+          for (int a = 0; a < NACC; ++a) {
+            if constexpr (BF) acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i][m], bf[a][t], acc[a][i][m][t], 0, 0, 0);
+            else acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][m], bf[a][t], acc[a][i][m][t], 0, 0, 0);
+          }
+  };
   for (int s0 = 0; s0 < nsteps; s0 += KS) {
     const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
     if (s0 > 0) {
@@ -242,16 +279,13 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
     }
-#pragma unroll 2
-    for (int ss = 0; ss < ks; ++ss) {
-      const int s = s0 + ss;
-      int q = 4 * s + lg;
-      if (q >= npairs) q = npairs - 1;   // weight rows are zero there
-      const int tap = q / cpv, cb = q - tap * cpv;
+    auto load = [&](int ss, Frag (&bf)[NACC][NTW], Frag (&af)[RPW][MT]) {
+      int tap, cb;
+      pw.take(tap, cb);
       int dz = 0, dy, dx;
       if (D == 2) { dy = tap / G::W; dx = tap % G::W; }
       else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
-      typename std::conditional<BF, bf16x8, float>::type bf[NACC][NTW];
+      const int aoff = ((dz * G::HY + dy) * G::HX + dx) * stride + cb * KV;
 #pragma unroll
       for (int a = 0; a < NACC; ++a)
 #pragma unroll
@@ -261,33 +295,29 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
           else bf[a][t] = reinterpret_cast<const float*>(bsm)[o];
         }
 #pragma unroll
-      for (int i = 0; i < RPW; ++i) {
-        const int rho = wave + 4 * i;
-        const int wy = rho % G::TY, wz = rho / G::TY;
+      for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-          const int ox = m * 16 + li;   // output x inside the tile
-          int hx, hy, hz;
-          if (MODE == CONV_S2) { hx = 2 * ox + dx; hy = 2 * wy + dy; hz = 2 * wz + dz; }
-          else { hx = ox + dx; hy = wy + dy; hz = wz + dz; }
-          const size_t node = ((size_t)hz * G::HY + hy) * G::HX + hx;
-          if constexpr (BF) {
-            const bf16x8 af = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) +
-                                                               node * stride + cb * KV);
-#pragma unroll
-            for (int t = 0; t < NTW; ++t)
-#pragma unroll
-              for (int a = 0; a < NACC; ++a)
-                acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[a][t], acc[a][i][m][t], 0, 0, 0);
-          } else {
-            const float af = reinterpret_cast<const float*>(smem)[node * stride + cb];
-#pragma unroll
-            for (int t = 0; t < NTW; ++t)
-#pragma unroll
-              for (int a = 0; a < NACC; ++a)
-                acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[a][t], acc[a][i][m][t], 0, 0, 0);
-          }
+          if constexpr (BF) af[i][m] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) + abase[i][m] + aoff);
+          else af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
         }
+    };
+    Frag b0[NACC][NTW], a0[RPW][MT];
+    if constexpr (PREF) {
+      Frag b1[NACC][NTW], a1[RPW][MT];
+      load(0, b0, a0);
+      int ss = 0;
+      for (; ss + 1 < ks; ss += 2) {
+        load(ss + 1, b1, a1);
+        mma(b0, a0);
+        if (ss + 2 < ks) load(ss + 2, b0, a0);
+        mma(b1, a1);
+      }
+      if (ss < ks) mma(b0, a0);
+    } else {
+      for (int ss = 0; ss < ks; ++ss) {
+        load(ss, b0, a0);
+        mma(b0, a0);
       }
     }
   }

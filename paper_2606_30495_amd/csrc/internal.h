@@ -51,6 +51,35 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return (t + ((n - t) >> 1)) >> (f.l - 1);
 }
 
+// Walk over the GEMM pair index q = 4 s + lg (s = 0, 1, ...) of the
+// matrix-core convolutions: (tap, cb) = (q / cpv, q % cpv) with q clamped to
+// npairs - 1 (weight rows past npairs are zero), advanced one step at a time
+// without a division (4 = d4 cpv + r4, so cb wraps at most once per step).
+struct PairWalk {
+  int q, tap, cb, cpv, d4, r4, npairs, tapL, cbL;
+  __device__ __forceinline__ void init(int lg, int cpv_, int npairs_) {
+    cpv = cpv_;
+    npairs = npairs_;
+    q = lg;
+    tap = lg / cpv;
+    cb = lg - tap * cpv;
+    d4 = 4 / cpv;
+    r4 = 4 - d4 * cpv;
+    tapL = (npairs - 1) / cpv;
+    cbL = npairs - 1 - tapL * cpv;
+  }
+  // (tap, cb) of the current step, then advance to the next
+  __device__ __forceinline__ void take(int& t, int& c) {
+    const bool over = q >= npairs;
+    t = over ? tapL : tap;
+    c = over ? cbL : cb;
+    q += 4;
+    tap += d4;
+    cb += r4;
+    if (cb >= cpv) { cb -= cpv; ++tap; }
+  }
+};
+
 enum ConvMode { CONV_S1 = 0, CONV_S2 = 1, CONV_T2 = 2 };
 enum ConvEpi {
   EPI_SET = 0,    // y = acc

@@ -40,14 +40,24 @@ struct SGeo {
   static constexpr int NCOL = 16 * NCT;
 };
 
+// Direct global-to-LDS copy of 16 bytes per lane: lane l of the wave writes
+// lds_wave + 16 l (lds_wave the same in every lane); inactive lanes write
+// nothing.  Completion is counted by vmcnt of the issuing wave.
+__device__ __forceinline__ void slds_copy16(const void* g, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
+}
+
 // One phase: for the region's row tiles (16 consecutive region nodes each,
 // split over the 4 waves in groups of GR), acc[a] = sum over K of
 // A(src region, tap offsets) x B(weights of tensor a); then `epi` stores
-// the results.  Weights stream through LDS in chunks of `kc` K-steps.
-template <bool BF, int NCT, int NACC, int GR, class Epi>
+// the results.  The global operands of the epilogue are fetched by `pre`
+// before the group's K loop, so their latency overlaps it.  Weights stream
+// through LDS in chunks of up to `kc` K-steps, laid out [a][4 ks rows][BROW]
+// (chunk vector idx at byte 16 idx) and copied straight from global memory.
+template <bool BF, int NCT, int NACC, int GR, class Pre, class Epi>
 __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src, int srcW, int dstW,
                                        int ndst, const void* w0, const void* w1,
-                                       unsigned char* wbuf, int kc, Epi epi) {
+                                       unsigned char* wbuf, int kc, Pre pre, Epi epi) {
   constexpr int KV = BF ? 8 : 1, ES = BF ? 2 : 4;
   constexpr int BROW = NCT * 16 * KV;           // elements of one pair row of the weights
   constexpr int V16 = BROW * ES / 16;
@@ -81,61 +91,89 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
       const int hy = n / dstW, hx = n - hy * dstW;
       snode[i] = hy * srcW + hx;                 // tap (0, 0) of the halo-1 source
     }
+    int sbase[GR];                               // LDS element offset of tap (0, 0)
+#pragma unroll
+    for (int i = 0; i < GR; ++i) sbase[i] = snode[i] * stride;
+    PairWalk pw;
+    pw.init(lg, cpv, npairs);
+    // epilogue operands: lane (li, lg) holds rows 4 lg + rr of each tile, column li
+    float2 ops[GR][NCT][4];
+#pragma unroll
+    for (int i = 0; i < GR; ++i)
+#pragma unroll
+      for (int t = 0; t < NCT; ++t)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int n = (wave + 4 * (g * GR + i)) * 16 + 4 * lg + rr;
+          ops[i][t][rr] = (live[i] && n < ndst) ? pre(n, t * 16 + li) : make_float2(0.f, 0.f);
+        }
     for (int s0 = 0; s0 < nsteps; s0 += kc) {
       const int ks = (nsteps - s0) < kc ? (nsteps - s0) : kc;
       if (!resident || (g == 0 && s0 == 0)) {
         __syncthreads();                         // previous chunk consumed
         const int total = NACC * 4 * ks * V16;
-        for (int idx = threadIdx.x; idx < total; idx += 256) {
-          const int a = idx / (4 * ks * V16), rem = idx % (4 * ks * V16);
-          const int row = rem / V16, vv = rem % V16;
-          const uint4 v = *reinterpret_cast<const uint4*>(
-              reinterpret_cast<const unsigned char*>(a ? w1 : w0) +
-              ((size_t)(4 * s0 + row) * ncols * KV) * ES + (size_t)vv * 16);
-          *reinterpret_cast<uint4*>(wbuf + (((size_t)a * 4 * kc + row) * BROW) * ES + (size_t)vv * 16) = v;
+        for (int base = wave * 64; base < total; base += 256) {
+          const int idx = base + lane;
+          if (idx < total) {
+            const int a = idx / (4 * ks * V16), rem = idx % (4 * ks * V16);
+            const int row = rem / V16, vv = rem % V16;
+            slds_copy16(reinterpret_cast<const unsigned char*>(a ? w1 : w0) +
+                            ((size_t)(4 * s0 + row) * ncols * KV) * ES + (size_t)vv * 16,
+                        wbuf + (size_t)__builtin_amdgcn_readfirstlane(base) * 16);
+          }
         }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies are in LDS
         __syncthreads();
       }
-      for (int ss = 0; ss < ks; ++ss) {
+      // Row tiles past the region (live false) are computed on a clamped,
+      // valid node and discarded, so no branch splits a step's LDS reads.
+      // The fragments of step ss + 1 are read before the products of step ss
+      // are issued (two register sets), so LDS latency overlaps the matrix
+      // cores; every accumulator still takes the steps in order.
+      typedef typename std::conditional<BF, sbf16x8, float>::type Frag;
+      // steps are loaded in order, so the pair walk advances once per call
+      auto load = [&](int ss, Frag (&bfr)[NACC][NCT], Frag (&af)[GR]) {
         const int s = s0 + ss;
-        int q = 4 * s + lg;
-        if (q >= npairs) q = npairs - 1;         // weight rows are zero there
-        const int tap = q / cpv, cb = q - tap * cpv;
-        const int toff = (tap / 3) * srcW + (tap % 3);
+        int tap, cb;
+        pw.take(tap, cb);
+        const int aoff = ((tap / 3) * srcW + (tap % 3)) * stride + cb * KV;
         const int wrow = resident ? s : ss;
-        typename std::conditional<BF, sbf16x8, float>::type bfr[NACC][NCT];
 #pragma unroll
         for (int a = 0; a < NACC; ++a)
 #pragma unroll
           for (int t = 0; t < NCT; ++t) {
-            const size_t o = ((size_t)a * 4 * kc + 4 * wrow + lg) * BROW + (t * 16 + li) * KV;
+            const size_t o = ((size_t)a * 4 * ks + 4 * wrow + lg) * BROW + (t * 16 + li) * KV;
             if constexpr (BF) bfr[a][t] = *reinterpret_cast<const sbf16x8*>(reinterpret_cast<const unsigned short*>(wbuf) + o);
             else bfr[a][t] = reinterpret_cast<const float*>(wbuf)[o];
           }
 #pragma unroll
         for (int i = 0; i < GR; ++i) {
-          if (!live[i]) continue;
-          const size_t node = (size_t)(snode[i] + toff);
-          if constexpr (BF) {
-            const sbf16x8 af = *reinterpret_cast<const sbf16x8*>(
-                reinterpret_cast<const unsigned short*>(src) + node * stride + cb * KV);
-#pragma unroll
-            for (int t = 0; t < NCT; ++t)
-#pragma unroll
-              for (int a = 0; a < NACC; ++a)
-                acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[a][t], acc[a][i][t], 0, 0, 0);
-          } else {
-            const float af = reinterpret_cast<const float*>(src)[node * stride + cb];
-#pragma unroll
-            for (int t = 0; t < NCT; ++t)
-#pragma unroll
-              for (int a = 0; a < NACC; ++a)
-                acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bfr[a][t], acc[a][i][t], 0, 0, 0);
-          }
+          if constexpr (BF) af[i] = *reinterpret_cast<const sbf16x8*>(reinterpret_cast<const unsigned short*>(src) + sbase[i] + aoff);
+          else af[i] = reinterpret_cast<const float*>(src)[sbase[i] + aoff];
         }
+      };
+      auto mma = [&](const Frag (&bfr)[NACC][NCT], const Frag (&af)[GR]) {
+#pragma unroll
+        for (int i = 0; i < GR; ++i)
+#pragma unroll
+          for (int t = 0; t < NCT; ++t)
+#pragma unroll
+            for (int a = 0; a < NACC; ++a) {
+              if constexpr (BF) acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[a][t], acc[a][i][t], 0, 0, 0);
+              else acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[a][t], acc[a][i][t], 0, 0, 0);
+            }
+      };
+      Frag b0[NACC][NCT], a0[GR], b1[NACC][NCT], a1[GR];
+      load(0, b0, a0);
+      int ss = 0;
+      for (; ss + 1 < ks; ss += 2) {
+        load(ss + 1, b1, a1);
+        mma(b0, a0);
+        if (ss + 2 < ks) load(ss + 2, b0, a0);
+        mma(b1, a1);
       }
+      if (ss < ks) mma(b0, a0);
     }
-    // results: lane (li, lg) holds rows 4 lg + rr of each tile, column li
 #pragma unroll
     for (int i = 0; i < GR; ++i) {
       if (!live[i]) continue;
@@ -145,7 +183,7 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           const int n = tile * 16 + 4 * lg + rr;
-          if (n < ndst) epi(n, t * 16 + li, acc[0][i][t][rr], acc[NACC - 1][i][t][rr]);
+          if (n < ndst) epi(n, t * 16 + li, acc[0][i][t][rr], acc[NACC - 1][i][t][rr], ops[i][t][rr]);
         }
     }
   }
@@ -177,27 +215,49 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
     if constexpr (BF) reinterpret_cast<unsigned short*>(buf)[(size_t)node * stride + c] = sf2bf(v);
     else reinterpret_cast<float*>(buf)[(size_t)node * stride + c] = v;
   };
-  // stage a FP32 field [nodes][C] on a region of width W, height H, halo h
+  // stage a FP32 field [nodes][C] on a region of width W, height H, halo h;
+  // loads are issued in batches of SB per thread before any LDS store
   auto stage = [&](unsigned char* buf, const float* __restrict__ f, int W, int H, int h) {
+    constexpr int SB = 8;
     const int ng = cinp / 4;
     const int total = W * H * ng;
     const bool vec4 = (C % 4) == 0;
-    for (int idx = threadIdx.x; idx < total; idx += 256) {
-      const int node = idx / ng, c = (idx % ng) * 4;
-      const int hy = node / W, hx = node - hy * W;
-      const int gy = y0 - h + hy, gx = x0 - h + hx;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (inside(gy, gx) && c < C) {
-        const float* p = f + ((size_t)gy * NX + gx) * C + c;
-        if (vec4) v = *reinterpret_cast<const float4*>(p);
-        else {
-          v.x = p[0];
-          if (c + 1 < C) v.y = p[1];
-          if (c + 2 < C) v.z = p[2];
-          if (c + 3 < C) v.w = p[3];
+    for (int base = threadIdx.x; base < total; base += 256 * SB) {
+      float4 v[SB];
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        const int hy = node / W, hx = node - hy * W;
+        const int gy = y0 - h + hy, gx = x0 - h + hx;
+        if (inside(gy, gx) && c < C) {
+          const float* p = f + ((size_t)gy * NX + gx) * C + c;
+          if (vec4) v[k] = *reinterpret_cast<const float4*>(p);
+          else {
+            v[k].x = p[0];
+            if (c + 1 < C) v[k].y = p[1];
+            if (c + 2 < C) v[k].z = p[2];
+            if (c + 3 < C) v[k].w = p[3];
+          }
         }
       }
-      put(buf, node, c, v.x); put(buf, node, c + 1, v.y); put(buf, node, c + 2, v.z); put(buf, node, c + 3, v.w);
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int idx = base + k * 256;
+        if (idx >= total) continue;
+        const int node = idx / ng, c = (idx % ng) * 4;
+        if constexpr (BF) {
+          // four bf16 values in one 8-byte store (node rows are 16-byte
+          // aligned, c is a multiple of 4)
+          const unsigned lo = (unsigned)sf2bf(v[k].x) | ((unsigned)sf2bf(v[k].y) << 16);
+          const unsigned hi = (unsigned)sf2bf(v[k].z) | ((unsigned)sf2bf(v[k].w) << 16);
+          *reinterpret_cast<uint2*>(reinterpret_cast<unsigned short*>(buf) + (size_t)node * stride + c) = make_uint2(lo, hi);
+        } else {
+          put(buf, node, c, v[k].x); put(buf, node, c + 1, v[k].y); put(buf, node, c + 2, v[k].z); put(buf, node, c + 3, v[k].w);
+        }
+      }
     }
   };
   constexpr int GR1 = (8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1;
@@ -210,38 +270,59 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
     stage(b02, A.e, G::W0, G::H0, 3);
     // (the chunk loop's first barrier orders the staging before any read)
     sphase<BF, NCT, 2, GR1>(A, b02, G::W0, G::W1, G::N1, A.wW, A.wKA, wbuf, A.kc1,
-        [&](int n, int c, float aw, float aka) {
+        [&](int n, int c) {
+          const int hy = n / G::W1, hx = n - hy * G::W1;
+          const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
+          float2 v = make_float2(0.f, 0.f);
+          if (c < C && inside(gy, gx)) {
+            const size_t o = ((size_t)gy * NX + gx) * C + c;
+            v = make_float2(A.r[o], A.a[o]);
+          }
+          return v;
+        },
+        [&](int n, int c, float aw, float aka, float2 ra) {
           if (c >= cinp) return;
           const int hy = n / G::W1, hx = n - hy * G::W1;
           const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
           float v = 0.f;
-          if (c < C && inside(gy, gx)) {
-            const size_t o = ((size_t)gy * NX + gx) * C + c;
-            v = A.r[o] - aw - A.a[o] * aka;
-          }
+          if (c < C && inside(gy, gx)) v = ra.x - aw - ra.y * aka;
           put(b1, n, c, v);
         });
   }
   __syncthreads();
   // ---- phase 2: u = s (.) (KS * t) on R2 (into the R0 storage)
   sphase<BF, NCT, 1, GR2>(A, b1, G::W1, G::W2, G::N2, A.wKS, nullptr, wbuf, A.kc2,
-      [&](int n, int c, float acc, float) {
+      [&](int n, int c) {
+        const int hy = n / G::W2, hx = n - hy * G::W2;
+        const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
+        float2 v = make_float2(0.f, 0.f);
+        if (c < C && inside(gy, gx)) v.x = A.s[((size_t)gy * NX + gx) * C + c];
+        return v;
+      },
+      [&](int n, int c, float acc, float, float2 sv) {
         if (c >= cinp) return;
         const int hy = n / G::W2, hx = n - hy * G::W2;
         const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
         float v = 0.f;
-        if (c < C && inside(gy, gx)) v = A.s[((size_t)gy * NX + gx) * C + c] * acc;
+        if (c < C && inside(gy, gx)) v = sv.x * acc;
         put(b02, n, c, v);
       });
   __syncthreads();
   // ---- phase 3: e' = e + Wsm * u on the tile
   sphase<BF, NCT, 1, GR2>(A, b02, G::W2, G::TX, G::N3, A.wSM, nullptr, wbuf, A.kc2,
-      [&](int n, int c, float acc, float) {
+      [&](int n, int c) {
+        const int hy = n / G::TX, hx = n - hy * G::TX;
+        const int gy = y0 + hy, gx = x0 + hx;
+        float2 v = make_float2(0.f, 0.f);
+        if (VAR != L1_FIRST && c < C && inside(gy, gx)) v.x = A.e[((size_t)gy * NX + gx) * C + c];
+        return v;
+      },
+      [&](int n, int c, float acc, float, float2 ev) {
         const int hy = n / G::TX, hx = n - hy * G::TX;
         const int gy = y0 + hy, gx = x0 + hx;
         if (c >= C || !inside(gy, gx)) return;
         const size_t o = ((size_t)gy * NX + gx) * C + c;
-        A.eo[o] = (VAR == L1_FIRST) ? acc : A.e[o] + acc;
+        A.eo[o] = (VAR == L1_FIRST) ? acc : ev.x + acc;
       });
 }
 
