@@ -21,8 +21,8 @@ typedef unsigned short u16;
 // Direct global-to-LDS copy of 16 bytes per lane: lane l of the wave writes
 // lds_wave + 16 l (lds_wave must be the same in every lane); inactive lanes
 // write nothing.  Completion is counted by vmcnt of the issuing wave.
-__device__ __forceinline__ void lds_copy16(const void* g, void* lds_wave) {
-  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
+__device__ __forceinline__ void lds_copy16(gptr<const unsigned char> g, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds((gptr<void>)g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
 }
 
 __device__ __forceinline__ u16 f2bf(float f) {
@@ -61,12 +61,12 @@ constexpr bool tile_ok() {
 // problem's grid (the batched wrapper maps the launch's blocks onto problems).
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
 __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
-  const float* __restrict__ x = A.x;
-  const void* __restrict__ wA = A.wA;
-  const void* __restrict__ wB = A.wB;
-  float* __restrict__ y = A.y;
-  const float* __restrict__ r = A.r;
-  const float* __restrict__ feat = A.feat;
+  const gptr<const float> __restrict__ x = to_global<const float>(A.x);
+  const gptr<const unsigned char> wA = to_global<const unsigned char>(A.wA);
+  const gptr<const unsigned char> wB = to_global<const unsigned char>(A.wB);
+  const gptr<float> __restrict__ y = to_global<float>(A.y);
+  const gptr<const float> __restrict__ r = to_global<const float>(A.r);
+  const gptr<const float> __restrict__ feat = to_global<const float>(A.feat);
   const int cin = A.cin, cinp = A.cinp, cout = A.cout, ncols = A.ncols, nsteps = A.nsteps;
   const int npairs = A.npairs, tiles_x = A.tiles_x, tiles_y = A.tiles_y, tiles_z = A.tiles_z;
   const int kchunk = A.kchunk;
@@ -114,8 +114,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     const int nrow = 4 * ks;
     const int a = idx / (nrow * V16), rem = idx % (nrow * V16);
     const int row = rem / V16, vv = rem % V16;
-    return reinterpret_cast<const unsigned char*>(a ? wB : wA) +
-           (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)vv * 16;
+    return (a ? wB : wA) + (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)vv * 16;
   };
   auto wfetch = [&](int s0, int ks) {
     const int total = NACC * 4 * ks * V16;
@@ -148,7 +147,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
         if (gx >= 0 && gx < IX && gy >= 0 && gy < IY && gz >= 0 && gz < IZ && c < cin) {
           const long long g = (((long long)gz * IY + gy) * IX + gx) * cin;
           if (vec4) {
-            v[k] = *reinterpret_cast<const float4*>(x + g + c);
+            v[k] = gld((gptr<const float4>)(x + g + c), 0);
           } else {
             v[k].x = x[g + c];
             if (c + 1 < cin) v[k].y = x[g + c + 1];

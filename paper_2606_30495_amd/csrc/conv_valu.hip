@@ -22,10 +22,10 @@ namespace mcmg {
 
 namespace {
 
-__device__ __forceinline__ float load_as_f32(const float* p, long long i) { return p[i]; }
-__device__ __forceinline__ float load_as_f32(const double* p, long long i) { return (float)p[i]; }
-__device__ __forceinline__ void store_from_f32(float* p, long long i, float v) { p[i] = v; }
-__device__ __forceinline__ void store_from_f32(double* p, long long i, float v) { p[i] = (double)v; }
+__device__ __forceinline__ float load_as_f32(gptr<const float> p, long long i) { return p[i]; }
+__device__ __forceinline__ float load_as_f32(gptr<const double> p, long long i) { return (float)p[i]; }
+__device__ __forceinline__ void store_from_f32(gptr<float> p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void store_from_f32(gptr<double> p, long long i, float v) { p[i] = (double)v; }
 
 __device__ __forceinline__ float gelu_f(float x) {
   return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
@@ -33,12 +33,12 @@ __device__ __forceinline__ float gelu_f(float x) {
 
 template <int D, int CT, int MODE, int EPI, typename TIN, typename TOUT>
 __device__ __forceinline__ void conv_body(const DArgs& A, const int vblk) {
-  const TIN* __restrict__ x = reinterpret_cast<const TIN*>(A.x);
-  const float* __restrict__ w = A.w;
-  const float* __restrict__ w2 = A.w2;
-  TOUT* __restrict__ y = reinterpret_cast<TOUT*>(A.y);
-  const float* __restrict__ r = A.r;
-  const float* __restrict__ feat = A.feat;
+  const gptr<const TIN> __restrict__ x = to_global<const TIN>(A.x);
+  const gptr<const float> __restrict__ w = to_global<const float>(A.w);
+  const gptr<const float> __restrict__ w2 = to_global<const float>(A.w2);
+  const gptr<TOUT> __restrict__ y = to_global<TOUT>(A.y);
+  const gptr<const float> __restrict__ r = to_global<const float>(A.r);
+  const gptr<const float> __restrict__ feat = to_global<const float>(A.feat);
   const int cin = A.cin, cout = A.cout, cpad = A.cpad;
   const Dims in = A.in, out = A.out;
   const long long p = (long long)vblk * blockDim.x + threadIdx.x;
@@ -87,8 +87,8 @@ __device__ __forceinline__ void conv_body(const DArgs& A, const int vblk) {
     }
     if (!valid) continue;
     const long long src = (((long long)ii[0] * in.n[1] + ii[1]) * in.n[2] + ii[2]) * cin;
-    const float* wt = w + (long long)t * cin * cpad + chunk * CT;
-    const float* wt2 = (EPI == EPI_RESID) ? (w2 + (long long)t * cin * cpad + chunk * CT) : nullptr;
+    const gptr<const float> wt = w + (long long)t * cin * cpad + chunk * CT;
+    const gptr<const float> wt2 = (EPI == EPI_RESID) ? (w2 + (long long)t * cin * cpad + chunk * CT) : nullptr;
     for (int ci = 0; ci < cin; ++ci) {
       const float xv = load_as_f32(x, src + ci);
 #pragma unroll
@@ -105,7 +105,7 @@ __device__ __forceinline__ void conv_body(const DArgs& A, const int vblk) {
     const int c = chunk * CT + k;
     if (c >= cout) break;
     float v = acc[k];
-    if (EPI == EPI_ADD) v = load_as_f32((const TOUT*)y, dst + c) + v;
+    if (EPI == EPI_ADD) v = load_as_f32((gptr<const TOUT>)y, dst + c) + v;
     else if (EPI == EPI_MUL) v = feat[dst + c] * v;
     else if (EPI == EPI_GELU) v = gelu_f(v);
     else if (EPI == EPI_RESID) v = r[dst + c] - v - feat[dst + c] * acc2[k];
@@ -156,9 +156,9 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
   constexpr int EY = C2Y + 2, EX = C2X + 2, NE = EY * EX;
   constexpr int PE = (NE + 255) / 256, NO = C2Y * C2X, PO = (NO + 255) / 256;
   __shared__ float2 se[3 * NE];
-  const TIN* __restrict__ x = reinterpret_cast<const TIN*>(A.x);
-  TOUT* __restrict__ y = reinterpret_cast<TOUT*>(A.y);
-  const float* __restrict__ w = A.w;
+  const gptr<const TIN> __restrict__ x = to_global<const TIN>(A.x);
+  const gptr<TOUT> __restrict__ y = to_global<TOUT>(A.y);
+  const gptr<const float> __restrict__ w = to_global<const float>(A.w);
   const int NZ = A.out.n[0], NY = A.out.n[1], NX = A.out.n[2];
   const int tiles_x = (NX + C2X - 1) / C2X, tiles_y = (NY + C2Y - 1) / C2Y;
   const int ntiles = tiles_x * tiles_y * ((NZ + C2Z - 1) / C2Z);
@@ -204,7 +204,7 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
 #pragma unroll 1
       for (int dz = 0; dz < 3; ++dz) {
         const float2* P = se + ring3(z - 1 + dz) * NE;
-        const float* wz = w + dz * 9 * 4;                      // [tap][cin][cpad = 2]
+        const gptr<const float> wz = w + dz * 9 * 4;                      // [tap][cin][cpad = 2]
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
           const int to = (t / 3) * EX + (t % 3);
@@ -271,9 +271,9 @@ __device__ __forceinline__ void c22y_body(const DArgs& A, const int vblk) {
   constexpr int EY = C2Y2 + 2, EX = C2X + 2, NE = EY * EX;
   constexpr int PE = (NE + 255) / 256, NO = C2Y2 * C2X, PO = (NO + 255) / 256;
   __shared__ float2 se[NE];
-  const TIN* __restrict__ x = reinterpret_cast<const TIN*>(A.x);
-  TOUT* __restrict__ y = reinterpret_cast<TOUT*>(A.y);
-  const float* __restrict__ w = A.w;
+  const gptr<const TIN> __restrict__ x = to_global<const TIN>(A.x);
+  const gptr<TOUT> __restrict__ y = to_global<TOUT>(A.y);
+  const gptr<const float> __restrict__ w = to_global<const float>(A.w);
   const int NY = A.out.n[0], NX = A.out.n[1];
   const int tiles_x = (NX + C2X - 1) / C2X;
   const int ntiles = tiles_x * ((NY + C2Y2 - 1) / C2Y2);

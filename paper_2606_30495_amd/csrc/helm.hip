@@ -45,11 +45,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // Complex values as one vector load (16 B for double, 8 B for float).
 __device__ __forceinline__ cplx ldv(const double* p, long long i) {
-  const double2 v = reinterpret_cast<const double2*>(p)[i];
+  const double2 v = gld(to_global<const double2>(p), i);
   return {v.x, v.y};
 }
 __device__ __forceinline__ cplx ldv(const float* p, long long i) {
-  const float2 v = reinterpret_cast<const float2*>(p)[i];
+  const float2 v = gld(to_global<const float2>(p), i);
   return {(double)v.x, (double)v.y};
 }
 
@@ -94,10 +94,10 @@ template <int D, typename TIN, int MODE>
 __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
   const TIN* __restrict__ u = reinterpret_cast<const TIN*>(A.u);
   const double* __restrict__ f = A.f;
-  double* __restrict__ out = A.out;
-  const double* __restrict__ k2 = A.op.k2;
+  const gptr<double> __restrict__ out = to_global<double>(A.out);
+  const gptr<const double> __restrict__ k2 = to_global<const double>(A.op.k2);
   const Dims n = A.op.ext;
-  double* __restrict__ partial = A.partial;
+  const gptr<double> __restrict__ partial = to_global<double>(A.partial);
   __shared__ double sh[HB / 64];
   double nrm = 0.0;
   const long long base = (long long)vblk * HB * HPT;
@@ -127,7 +127,7 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
     double gs = 0.0;
     if (A.op.gmax != 0.0) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) gs += A.op.g[a][i[a]];
+      for (int a = 0; a < D; ++a) gs += to_global<const double>(A.op.g[a])[i[a]];
     }
     cplx m[D], pc[D], cmw[D], cpw[D], um[D], up[D];
 #pragma unroll
@@ -169,7 +169,7 @@ __device__ __forceinline__ void helm_body(const HArgs& A, const int vblk) {
       acc.re = fc.re - acc.re;
       acc.im = fc.im - acc.im;
     }
-    reinterpret_cast<double2*>(out)[p] = make_double2(acc.re, acc.im);
+    ((gptr<nvd2>)out)[p] = nvd2{acc.re, acc.im};
     nrm += acc.re * acc.re + acc.im * acc.im;
   }
   if (partial) {
@@ -208,7 +208,7 @@ template <typename TIN>
 __global__ __launch_bounds__(MX * MY) void helm_march_kernel(HArgs A, int ntiles) {
   const TIN* __restrict__ u = reinterpret_cast<const TIN*>(A.u);
   double2* __restrict__ out = reinterpret_cast<double2*>(A.out);
-  const double* __restrict__ k2 = A.op.k2;
+  const gptr<const double> __restrict__ k2 = to_global<const double>(A.op.k2);
   const int NZ = A.op.ext.n[0], NY = A.op.ext.n[1], NX = A.op.ext.n[2];
   const int per = (ntiles + 7) / 8;
   const int tl = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-contiguous bands
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(MX * MY) void helm_march_kernel(HArgs A, int ntiles
   const cplx m1 = ldv(A.op.cm[1], gy), p1 = ldv(A.op.cp[1], gy);
   const cplx m2 = ldv(A.op.cm[2], gx), p2 = ldv(A.op.cp[2], gx);
   const bool sp = A.op.gmax != 0.0;
-  const double g1 = sp ? A.op.g[1][gy] : 0.0, g2 = sp ? A.op.g[2][gx] : 0.0;
+  const double g1 = sp ? to_global<const double>(A.op.g[1])[gy] : 0.0, g2 = sp ? to_global<const double>(A.op.g[2])[gx] : 0.0;
   // in-plane neighbours of plane z: y-1, y+1, x-1, x+1 (zero outside the grid)
   auto nbrs = [&](int z, cplx* nb) {
     const long long c = (long long)z * plane + col;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(MX * MY) void helm_march_kernel(HArgs A, int ntiles
     um[2] = nb[2]; up[2] = nb[3];
     double gs = 0.0;
     if (sp) {
-      gs += A.op.g[0][z];
+      gs += to_global<const double>(A.op.g[0])[z];
       gs += g1;
       gs += g2;
     }

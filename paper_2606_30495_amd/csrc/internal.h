@@ -51,6 +51,32 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv& f) {
   return (t + ((n - t) >> 1)) >> (f.l - 1);
 }
 
+// Pointer to global memory.  Accesses through it are global instructions
+// even when the pointer value was read from memory (the per-problem argument
+// tables of the batched kernels), where a plain pointer gives flat
+// instructions, which also count against the LDS wait counter.
+template <class T> using gptr = __attribute__((address_space(1))) T*;
+template <class T, class U> __device__ __forceinline__ gptr<T> to_global(U* p) { return (gptr<T>)p; }
+// HIP's float2/float4/double2 cannot be read or written in place through
+// such a pointer (their copy operations take generic references): these go
+// through the compiler's own vector types.
+typedef float nvf2 __attribute__((ext_vector_type(2)));
+typedef float nvf4 __attribute__((ext_vector_type(4)));
+typedef double nvd2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 gld(gptr<const float2> p, long long i) {
+  const nvf2 v = ((gptr<const nvf2>)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 gld(gptr<const float4> p, long long i) {
+  const nvf4 v = ((gptr<const nvf4>)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 gld(gptr<const double2> p, long long i) {
+  const nvd2 v = ((gptr<const nvd2>)p)[i];
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void gst(gptr<float2> p, long long i, float2 v) { ((gptr<nvf2>)p)[i] = nvf2{v.x, v.y}; }
+
 // Walk over the GEMM pair index q = 4 s + lg (s = 0, 1, ...) of the
 // matrix-core convolutions: (tap, cb) = (q / cpv, q % cpv) with q clamped to
 // npairs - 1 (weight rows past npairs are zero), advanced one step at a time

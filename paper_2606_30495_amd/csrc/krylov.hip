@@ -40,9 +40,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
-__device__ __forceinline__ void multidot_body(const double* __restrict__ V, long long ldv, int nvec,
-                                              const double* __restrict__ w, long long n,
-                                              double* __restrict__ partial, int nb, int vblk) {
+__device__ __forceinline__ void multidot_body(const double* __restrict__ V_, long long ldv, int nvec,
+                                              const double* __restrict__ w_, long long n,
+                                              double* __restrict__ partial_, int nb, int vblk) {
+  const gptr<const double> V = to_global<const double>(V_), w = to_global<const double>(w_);
+  const gptr<double> partial = to_global<double>(partial_);
   __shared__ double sh[RB / 64];
   const long long base = (long long)vblk * RB * RPT;
   double wr[RPT], wi[RPT];
@@ -53,7 +55,7 @@ __device__ __forceinline__ void multidot_body(const double* __restrict__ V, long
     else { wr[q] = 0.0; wi[q] = 0.0; }
   }
   for (int i = 0; i < nvec; ++i) {
-    const double* v = V + (long long)i * 2 * ldv;
+    const gptr<const double> v = V + (long long)i * 2 * ldv;
     double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -106,9 +108,11 @@ __device__ __forceinline__ void reduce_dots_body(const double* __restrict__ part
   }
 }
 
-__device__ __forceinline__ void update_body(const double* __restrict__ V, long long ldv, int nvec,
-                                            const double* __restrict__ coef, double* __restrict__ w,
-                                            long long n, double* __restrict__ partial, int vblk) {
+__device__ __forceinline__ void update_body(const double* __restrict__ V_, long long ldv, int nvec,
+                                            const double* __restrict__ coef_, double* __restrict__ w_,
+                                            long long n, double* __restrict__ partial_, int vblk) {
+  const gptr<const double> V = to_global<const double>(V_), coef = to_global<const double>(coef_);
+  const gptr<double> w = to_global<double>(w_), partial = to_global<double>(partial_);
   __shared__ double sh[RB / 64];
   const long long base = (long long)vblk * RB * RPT;
   double s2 = 0.0;
@@ -119,7 +123,7 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V, long l
     double ar = w[2 * p], ai = w[2 * p + 1];
     for (int i = 0; i < nvec; ++i) {
       const double cr = coef[2 * i], ci = coef[2 * i + 1];
-      const double* v = V + (long long)i * 2 * ldv;
+      const gptr<const double> v = V + (long long)i * 2 * ldv;
       const double vr = v[2 * p], vi = v[2 * p + 1];
       ar -= cr * vr - ci * vi;
       ai -= cr * vi + ci * vr;
@@ -216,13 +220,16 @@ __device__ __forceinline__ void backsolve_body(const double* H, int ldh, int k, 
   }
 }
 
-__device__ __forceinline__ void zupdate_body(const float* __restrict__ Z, long long ldz, int k,
-                                             const double* __restrict__ y, double* __restrict__ u,
+__device__ __forceinline__ void zupdate_body(const float* __restrict__ Z_, long long ldz, int k,
+                                             const double* __restrict__ y_, double* __restrict__ u_,
                                              long long n, long long p) {
+  const gptr<const float> Z = to_global<const float>(Z_);
+  const gptr<const double> y = to_global<const double>(y_);
+  const gptr<double> u = to_global<double>(u_);
   if (p >= n) return;
   double ar = u[2 * p], ai = u[2 * p + 1];
   for (int i = 0; i < k; ++i) {
-    const float* z = Z + (long long)i * 2 * ldz;
+    const gptr<const float> z = Z + (long long)i * 2 * ldz;
     const double zr = z[2 * p], zi = z[2 * p + 1];
     const double yr = y[2 * i], yi = y[2 * i + 1];
     ar += yr * zr - yi * zi;
@@ -348,7 +355,7 @@ __global__ __launch_bounds__(RB) void kb_multidot(const KArgs* __restrict__ tab,
   const int p = batch_find(pre, np, blockIdx.x);
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  if (pass == 1 && A.skip[0]) return;
+  if (pass == 1 && to_global<const int>(A.skip)[0]) return;
   multidot_body(A.V, A.N, jpos[p] + 1, A.w, A.N, A.partial, red_blocks(A.N), blockIdx.x - pre[p]);
 }
 
@@ -361,7 +368,7 @@ __global__ __launch_bounds__(RB) void kb_reduce_dots(const KArgs* __restrict__ t
   const KArgs& A = tab[p];
   const int j = jpos[p];
   if ((int)blockIdx.x > j + 1) return;
-  if (pass == 1 && A.skip[0]) return;
+  if (pass == 1 && to_global<const int>(A.skip)[0]) return;
   reduce_dots_body(A.partial, red_blocks(A.N), j + 1, A.coef, A.H + 2LL * j * A.ldh,
                    A.scal + (pass == 0 ? 8 : 10), blockIdx.x);
 }
@@ -373,7 +380,7 @@ __global__ __launch_bounds__(RB) void kb_update(const KArgs* __restrict__ tab,
   const int p = batch_find(pre, np, blockIdx.x);
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  if (pass == 1 && A.skip[0]) return;
+  if (pass == 1 && to_global<const int>(A.skip)[0]) return;
   update_body(A.V, A.N, jpos[p] + 1, A.coef, A.w, A.N, A.partial, blockIdx.x - pre[p]);
 }
 
@@ -382,7 +389,7 @@ __global__ __launch_bounds__(RB) void kb_reduce_norm(const KArgs* __restrict__ t
   const int p = blockIdx.x;
   if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  if (pass == 1 && A.skip[0]) return;
+  if (pass == 1 && to_global<const int>(A.skip)[0]) return;
   reduce_norm_body(A.partial, red_blocks(A.N), A.scal + 8, A.scal + 9, A.skip, pass,
                    pass == 0 ? A.always_two : 0);
 }
@@ -408,9 +415,9 @@ __global__ __launch_bounds__(RB) void kb_scale(const KArgs* __restrict__ tab,
   const KArgs& A = tab[p];
   const long long q = (long long)(blockIdx.x - pre[p]) * RB + threadIdx.x;
   if (q >= A.N) return;
-  const double* src = mode == 0 ? A.r : A.w;
-  double* dst = A.V + (mode == 0 ? 0LL : 2LL * (jpos[p] + 1) * A.N);
-  const double inv = 1.0 / (mode == 0 ? A.scal[3] : A.scal[9]);
+  const gptr<const double> src = to_global<const double>(mode == 0 ? A.r : A.w);
+  const gptr<double> dst = to_global<double>(A.V) + (mode == 0 ? 0LL : 2LL * (jpos[p] + 1) * A.N);
+  const double inv = 1.0 / (mode == 0 ? to_global<const double>(A.scal)[3] : to_global<const double>(A.scal)[9]);
   dst[2 * q] = src[2 * q] * inv;
   dst[2 * q + 1] = src[2 * q + 1] * inv;
 }

@@ -49,15 +49,22 @@ __device__ __forceinline__ float uni(float v) {
   return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// p[i] if ok, else zero; the load is unconditional (index clamped to 0), so
+// the value select does not become a load through a selected pointer
+__device__ __forceinline__ float2 ldz(gptr<const float2> p, long long i, bool ok) {
+  const float2 v = gld(p, ok ? i : 0);
+  return ok ? v : make_float2(0.f, 0.f);
+}
+
 template <int D, int VAR, bool WL = false>
 __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, const int vblk) {
   static_assert(D == 2, "3D uses the z-streaming form");
   auto W_ = [](float v) { return WL ? uni(v) : v; };
-  const float2* __restrict__ e = reinterpret_cast<const float2*>(A.e);
-  float2* __restrict__ eo = reinterpret_cast<float2*>(A.eo);
-  const float2* __restrict__ r = reinterpret_cast<const float2*>(A.r);
-  const float2* __restrict__ a = reinterpret_cast<const float2*>(A.a);
-  const float2* __restrict__ s = reinterpret_cast<const float2*>(A.s);
+  const gptr<const float2> __restrict__ e = to_global<const float2>(A.e);
+  const gptr<float2> __restrict__ eo = to_global<float2>(A.eo);
+  const gptr<const float2> __restrict__ r = to_global<const float2>(A.r);
+  const gptr<const float2> __restrict__ a = to_global<const float2>(A.a);
+  const gptr<const float2> __restrict__ s = to_global<const float2>(A.s);
   using G = G1<2>;
   constexpr int TY = G::TY, TX = G::TX;
   constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // halo of the staged e
@@ -66,7 +73,9 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   constexpr int TYt = TY + 2 * TG, TXt = TX + 2 * TG, NT = TYt * TXt;
   constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
   constexpr int NO = TY * TX;
-  constexpr int RP = 4;                                   // points per thread per round
+  constexpr int RP = 4;                                   // points per thread per phase
+  static_assert(NT <= NTH * RP && NU <= NTH * RP && NO <= NTH * RP, "one round per phase");
+  constexpr int PE = (NE + NTH - 1) / NTH;                // staged e values per thread
   // LDS: `sa` holds e (halo H), then u (halo 1) once t exists; `sb` holds t.
   constexpr int NA = (VAR == L1_FIRST) ? NU : (VAR == L1_RESID ? NE : (NE > NU ? NE : NU));
   __shared__ float2 sa[NA];
@@ -82,44 +91,65 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   auto gidx = [&](int y, int x) { return (long long)y * NX + x; };
   const float2 zero = make_float2(0.f, 0.f);
 
-  // ---- stage e with halo H (a batch of loads per thread, then the stores)
+  // ---- every global operand of the block is requested up front, so the
+  // block waits for one memory latency instead of one per phase: e with
+  // halo H (staged in LDS), r and a on the t box, s on the u box, e on the
+  // tile.  A thread owns the same RP points of each box throughout.
+  float2 v[PE];
   if (VAR != L1_FIRST) {
-    constexpr int PE = (NE + NTH - 1) / NTH;
-#pragma unroll 1
-    for (int k0 = 0; k0 < PE; k0 += 8) {
-      float2 v[8];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int i = threadIdx.x + (k0 + k) * NTH;
-        const int y = i / EX, x = i % EX;
-        v[k] = (k0 + k < PE && i < NE && inside(y0 - H + y, x0 - H + x)) ? e[gidx(y0 - H + y, x0 - H + x)] : zero;
-      }
+    for (int k = 0; k < PE; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / EX, x = i % EX;
+      v[k] = ldz(e, gidx(y0 - H + y, x0 - H + x), i < NE && inside(y0 - H + y, x0 - H + x));
+    }
+  }
+  float2 rv[RP], av[RP];
+  int eb[RP];
+  bool okt[RP];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const int i = threadIdx.x + (k0 + k) * NTH;
-        if (k0 + k < PE && i < NE) sa[i] = v[k];
-      }
+  for (int k = 0; k < RP; ++k) {
+    const int i = threadIdx.x + k * NTH;
+    const int y = i / TXt, x = i % TXt;
+    const int gy = y0 - TG + y, gx = x0 - TG + x;
+    okt[k] = i < NT && inside(gy, gx);
+    rv[k] = ldz(r, gidx(gy, gx), okt[k]);
+    av[k] = (VAR != L1_FIRST) ? ldz(a, gidx(gy, gx), okt[k]) : zero;
+    eb[k] = (i < NT) ? (y + H - TG) * EX + (x + H - TG) : EX + 1;
+  }
+  float2 sv[RP], ev[RP];
+  int tb[RP], ub[RP];
+  bool oku[RP], oko[RP];
+  if (VAR != L1_RESID) {
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / UX, x = i % UX;
+      const int gy = y0 - 1 + y, gx = x0 - 1 + x;
+      oku[k] = i < NU && inside(gy, gx);
+      sv[k] = ldz(s, gidx(gy, gx), oku[k]);
+      tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
+    }
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      const int y = i / TX, x = i % TX;
+      oko[k] = i < NO && inside(y0 + y, x0 + x);
+      ub[k] = (i < NO) ? (y + 1) * UX + (x + 1) : UX + 1;
+      ev[k] = (VAR != L1_FIRST) ? ldz(e, gidx(y0 + y, x0 + x), oko[k]) : zero;
+    }
+  }
+  if (VAR != L1_FIRST) {
+#pragma unroll
+    for (int k = 0; k < PE; ++k) {
+      const int i = threadIdx.x + k * NTH;
+      if (i < NE) sa[i] = v[k];
     }
     __syncthreads();
   }
 
   // ---- t box: t = r - (W*e + a (.) (KA*e)) (FIRST: t = r; RESID: to memory)
-#pragma unroll 1
-  for (int r0 = 0; r0 < NT; r0 += NTH * RP) {
-    asm volatile("" ::: "memory");   // weights are re-read per round, not held in registers
-    float2 rv[RP], av[RP];
-    int eb[RP];
-    bool ok[RP];
-#pragma unroll
-    for (int k = 0; k < RP; ++k) {
-      const int i = r0 + threadIdx.x + k * NTH;
-      const int y = i / TXt, x = i % TXt;
-      const int gy = y0 - TG + y, gx = x0 - TG + x;
-      ok[k] = i < NT && inside(gy, gx);
-      rv[k] = ok[k] ? r[gidx(gy, gx)] : zero;
-      av[k] = (ok[k] && VAR != L1_FIRST) ? a[gidx(gy, gx)] : zero;
-      eb[k] = (i < NT) ? (y + H - TG) * EX + (x + H - TG) : EX + 1;
-    }
+  {
     float w0[RP], w1[RP], k0[RP], k1[RP];
 #pragma unroll
     for (int k = 0; k < RP; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
@@ -131,22 +161,22 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
         const float b00 = W_(w.KA[0][0][t]), b01 = W_(w.KA[0][1][t]), b10 = W_(w.KA[1][0][t]), b11 = W_(w.KA[1][1][t]);
 #pragma unroll
         for (int k = 0; k < RP; ++k) {
-          const float2 v = sa[eb[k] + to];
-          w0[k] = fmaf(a00, v.x, fmaf(a01, v.y, w0[k]));
-          w1[k] = fmaf(a10, v.x, fmaf(a11, v.y, w1[k]));
-          k0[k] = fmaf(b00, v.x, fmaf(b01, v.y, k0[k]));
-          k1[k] = fmaf(b10, v.x, fmaf(b11, v.y, k1[k]));
+          const float2 q = sa[eb[k] + to];
+          w0[k] = fmaf(a00, q.x, fmaf(a01, q.y, w0[k]));
+          w1[k] = fmaf(a10, q.x, fmaf(a11, q.y, w1[k]));
+          k0[k] = fmaf(b00, q.x, fmaf(b01, q.y, k0[k]));
+          k1[k] = fmaf(b10, q.x, fmaf(b11, q.y, k1[k]));
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
-      const int i = r0 + threadIdx.x + k * NTH;
+      const int i = threadIdx.x + k * NTH;
       if (i >= NT) continue;
-      const float2 tv = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
-                              : zero;
+      const float2 tv = okt[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
+                               : zero;
       if (VAR == L1_RESID) {
-        if (ok[k]) eo[gidx(y0 + i / TXt, x0 + i % TXt)] = tv;
+        if (okt[k]) gst(eo, gidx(y0 + i / TXt, x0 + i % TXt), tv);
       } else {
         sb[i] = tv;
       }
@@ -156,21 +186,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   __syncthreads();
 
   // ---- u box: u = s (.) (KS * t), into the e storage (e is not read again)
-#pragma unroll 1
-  for (int r0 = 0; r0 < NU; r0 += NTH * RP) {
-    asm volatile("" ::: "memory");
-    float2 sv[RP];
-    int tb[RP];
-    bool ok[RP];
-#pragma unroll
-    for (int k = 0; k < RP; ++k) {
-      const int i = r0 + threadIdx.x + k * NTH;
-      const int y = i / UX, x = i % UX;
-      const int gy = y0 - 1 + y, gx = x0 - 1 + x;
-      ok[k] = i < NU && inside(gy, gx);
-      sv[k] = ok[k] ? s[gidx(gy, gx)] : zero;
-      tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
-    }
+  {
     float c0[RP], c1[RP];
 #pragma unroll
     for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
@@ -180,35 +196,22 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
       const float a00 = W_(w.KS[0][0][t]), a01 = W_(w.KS[0][1][t]), a10 = W_(w.KS[1][0][t]), a11 = W_(w.KS[1][1][t]);
 #pragma unroll
       for (int k = 0; k < RP; ++k) {
-        const float2 v = sb[tb[k] + to];
-        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
-        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+        const float2 q = sb[tb[k] + to];
+        c0[k] = fmaf(a00, q.x, fmaf(a01, q.y, c0[k]));
+        c1[k] = fmaf(a10, q.x, fmaf(a11, q.y, c1[k]));
       }
     }
     // every thread has finished reading e from sa (barrier above) before u lands there
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
-      const int i = r0 + threadIdx.x + k * NTH;
-      if (i < NU) sa[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
+      const int i = threadIdx.x + k * NTH;
+      if (i < NU) sa[i] = oku[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
     }
   }
   __syncthreads();
 
-  // ---- output tile: e' = e + Wsm * u (e re-read from memory: still in L2)
-#pragma unroll 1
-  for (int r0 = 0; r0 < NO; r0 += NTH * RP) {
-    asm volatile("" ::: "memory");
-    int ub[RP];
-    bool ok[RP];
-    float2 ev[RP];
-#pragma unroll
-    for (int k = 0; k < RP; ++k) {
-      const int i = r0 + threadIdx.x + k * NTH;
-      const int y = i / TX, x = i % TX;
-      ok[k] = i < NO && inside(y0 + y, x0 + x);
-      ub[k] = (i < NO) ? (y + 1) * UX + (x + 1) : UX + 1;
-      ev[k] = (ok[k] && VAR != L1_FIRST) ? e[gidx(y0 + y, x0 + x)] : zero;
-    }
+  // ---- output tile: e' = e + Wsm * u
+  {
     float c0[RP], c1[RP];
 #pragma unroll
     for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
@@ -218,16 +221,16 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
       const float a00 = W_(w.Wsm[0][0][t]), a01 = W_(w.Wsm[0][1][t]), a10 = W_(w.Wsm[1][0][t]), a11 = W_(w.Wsm[1][1][t]);
 #pragma unroll
       for (int k = 0; k < RP; ++k) {
-        const float2 v = sa[ub[k] + to];
-        c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
-        c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+        const float2 q = sa[ub[k] + to];
+        c0[k] = fmaf(a00, q.x, fmaf(a01, q.y, c0[k]));
+        c1[k] = fmaf(a10, q.x, fmaf(a11, q.y, c1[k]));
       }
     }
 #pragma unroll
     for (int k = 0; k < RP; ++k) {
-      if (!ok[k]) continue;
-      const int i = r0 + threadIdx.x + k * NTH;
-      eo[gidx(y0 + i / TX, x0 + i % TX)] = make_float2(ev[k].x + c0[k], ev[k].y + c1[k]);
+      if (!oko[k]) continue;
+      const int i = threadIdx.x + k * NTH;
+      gst(eo, gidx(y0 + i / TX, x0 + i % TX), make_float2(ev[k].x + c0[k], ev[k].y + c1[k]));
     }
   }
 }
@@ -235,7 +238,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
 // Copy a weight set into LDS (all threads, then a barrier).
 __device__ __forceinline__ void stage_weights(const L1Weights* __restrict__ src, L1Weights* dst) {
   constexpr int NW = sizeof(L1Weights) / sizeof(float);
-  const float* s = reinterpret_cast<const float*>(src);
+  const gptr<const float> s = to_global<const float>(src);
   float* d = reinterpret_cast<float*>(dst);
   for (int i = threadIdx.x; i < NW; i += NTH) d[i] = s[i];
   __syncthreads();
@@ -260,11 +263,12 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
   __shared__ float2 st[(VAR == L1_RESID) ? 1 : 3 * NT];
   __shared__ float2 su[(VAR == L1_RESID) ? 1 : 3 * NU];
 
-  const float2* __restrict__ e = reinterpret_cast<const float2*>(A.e);
-  float2* __restrict__ eo = reinterpret_cast<float2*>(A.eo);
-  const float2* __restrict__ r = reinterpret_cast<const float2*>(A.r);
-  const float2* __restrict__ a = reinterpret_cast<const float2*>(A.a);
-  const float2* __restrict__ s = reinterpret_cast<const float2*>(A.s);
+  const gptr<const float2> __restrict__ e = to_global<const float2>(A.e);
+  const gptr<float2> __restrict__ eo = to_global<float2>(A.eo);
+  const gptr<const float2> __restrict__ r = to_global<const float2>(A.r);
+  const gptr<const float2> __restrict__ a = to_global<const float2>(A.a);
+  const gptr<const float2> __restrict__ s = to_global<const float2>(A.s);
+  const gptr<const L1Weights> wg = to_global<const L1Weights>(wp);
   const int NZ = A.n.n[0], NY = A.n.n[1], NX = A.n.n[2];
   const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
   const int per = (ntiles + 7) / 8;
@@ -287,7 +291,7 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
       const int i = threadIdx.x + j * NTH;
       const int y = i / EX, x = i % EX;
       const int gy = y0 - H + y, gx = x0 - H + x;
-      v[j] = (i < NE && inside(k, gy, gx)) ? e[gidx(k, gy, gx)] : zero;
+      v[j] = ldz(e, gidx(k, gy, gx), i < NE && inside(k, gy, gx));
     }
     float2* dst = se + ring(k, NER) * NE;
 #pragma unroll
@@ -299,12 +303,12 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
   // acc += (X * src)[point] over the 27 taps, src planes q-1, q, q+1 in a ring
   // (2 x 2 channel block X of the weight set `off` = W, KA, KS or Wsm).
   auto conv2 = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
-                   const float* Xw, const int* base, float* c0, float* c1, auto npts) {
+                   gptr<const float> Xw, const int* base, float* c0, float* c1, auto npts) {
     constexpr int NP = decltype(npts)::value;
 #pragma unroll 1
     for (int dz = 0; dz < 3; ++dz) {
       const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
-      const float* w = Xw + dz * 9;
+      const gptr<const float> w = Xw + dz * 9;
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
@@ -321,14 +325,14 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
   // as conv2 for two weight sets X (into c0, c1) and Y (into d0, d1) that read
   // each staged value once; every accumulator sums its taps in conv2's order
   auto conv2pair = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
-                       const float* Xw, const float* Yw, const int* base, float* c0, float* c1,
+                       gptr<const float> Xw, gptr<const float> Yw, const int* base, float* c0, float* c1,
                        float* d0, float* d1, auto npts) {
     constexpr int NP = decltype(npts)::value;
 #pragma unroll 1
     for (int dz = 0; dz < 3; ++dz) {
       const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
-      const float* w = Xw + dz * 9;
-      const float* y = Yw + dz * 9;
+      const gptr<const float> w = Xw + dz * 9;
+      const gptr<const float> y = Yw + dz * 9;
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
         const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
@@ -356,15 +360,15 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
       const int y = i / TXt, x = i % TXt;
       const int gy = y0 - 2 + y, gx = x0 - 2 + x;
       ok[k] = i < NT && inside(q, gy, gx);
-      rv[k] = ok[k] ? r[gidx(q, gy, gx)] : zero;
-      av[k] = (ok[k] && VAR != L1_FIRST) ? a[gidx(q, gy, gx)] : zero;
+      rv[k] = ldz(r, gidx(q, gy, gx), ok[k]);
+      av[k] = (VAR != L1_FIRST) ? ldz(a, gidx(q, gy, gx), ok[k]) : zero;
       eb[k] = (i < NT) ? (y + H - 2) * EX + (x + H - 2) : EX + 1;
     }
     float w0[PT], w1[PT], k0[PT], k1[PT];
 #pragma unroll
     for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
     if (VAR != L1_FIRST)
-      conv2pair(se, NER, NE, q, EX, &wp->W[0][0][0], &wp->KA[0][0][0], eb, w0, w1, k0, k1,
+      conv2pair(se, NER, NE, q, EX, &wg->W[0][0][0], &wg->KA[0][0][0], eb, w0, w1, k0, k1,
                 std::integral_constant<int, PT>());
     float2* dst = st + ring(q, 3) * NT;
 #pragma unroll
@@ -386,13 +390,13 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
       const int y = i / UX, x = i % UX;
       const int gy = y0 - 1 + y, gx = x0 - 1 + x;
       ok[k] = i < NU && inside(p, gy, gx);
-      sv[k] = ok[k] ? s[gidx(p, gy, gx)] : zero;
+      sv[k] = ldz(s, gidx(p, gy, gx), ok[k]);
       tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
     }
     float c0[PU], c1[PU];
 #pragma unroll
     for (int k = 0; k < PU; ++k) c0[k] = c1[k] = 0.f;
-    conv2(st, 3, NT, p, TXt, &wp->KS[0][0][0], tb, c0, c1, std::integral_constant<int, PU>());
+    conv2(st, 3, NT, p, TXt, &wg->KS[0][0][0], tb, c0, c1, std::integral_constant<int, PU>());
     float2* dst = su + ring(p, 3) * NU;
 #pragma unroll
     for (int k = 0; k < PU; ++k) {
@@ -414,7 +418,7 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
     float c0[PO], c1[PO];
 #pragma unroll
     for (int k = 0; k < PO; ++k) c0[k] = c1[k] = 0.f;
-    conv2(su, 3, NU, z, UX, &wp->Wsm[0][0][0], ub, c0, c1, std::integral_constant<int, PO>());
+    conv2(su, 3, NU, z, UX, &wg->Wsm[0][0][0], ub, c0, c1, std::integral_constant<int, PO>());
 #pragma unroll
     for (int k = 0; k < PO; ++k) {
       if (!ok[k]) continue;
@@ -422,7 +426,7 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
       const int y = i / TX, x = i % TX;
       float2 ev = zero;
       if (VAR == L1_STEP) ev = se[ring(z, NER) * NE + (y + H) * EX + (x + H)];
-      eo[gidx(z, y0 + y, x0 + x)] = make_float2(ev.x + c0[k], ev.y + c1[k]);
+      gst(eo, gidx(z, y0 + y, x0 + x), make_float2(ev.x + c0[k], ev.y + c1[k]));
     }
   };
 
@@ -441,22 +445,22 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
           const int i = threadIdx.x + j * NTH;
           const int y = i / TX, x = i % TX;
           ok[j] = i < NO && inside(z, y0 + y, x0 + x);
-          rv[j] = ok[j] ? r[gidx(z, y0 + y, x0 + x)] : zero;
-          av[j] = ok[j] ? a[gidx(z, y0 + y, x0 + x)] : zero;
+          rv[j] = ldz(r, gidx(z, y0 + y, x0 + x), ok[j]);
+          av[j] = ldz(a, gidx(z, y0 + y, x0 + x), ok[j]);
           eb[j] = (i < NO) ? (y + 1) * EX + (x + 1) : EX + 1;
         }
         float w0[PO], w1[PO], k0[PO], k1[PO];
 #pragma unroll
         for (int j = 0; j < PO; ++j) w0[j] = w1[j] = k0[j] = k1[j] = 0.f;
-        conv2pair(se, NER, NE, z, EX, &wp->W[0][0][0], &wp->KA[0][0][0], eb, w0, w1, k0, k1,
+        conv2pair(se, NER, NE, z, EX, &wg->W[0][0][0], &wg->KA[0][0][0], eb, w0, w1, k0, k1,
                   std::integral_constant<int, PO>());
 #pragma unroll
         for (int j = 0; j < PO; ++j) {
           if (!ok[j]) continue;
           const int i = threadIdx.x + j * NTH;
           const int y = i / TX, x = i % TX;
-          eo[gidx(z, y0 + y, x0 + x)] = make_float2(rv[j].x - w0[j] - av[j].x * k0[j],
-                                                    rv[j].y - w1[j] - av[j].y * k1[j]);
+          gst(eo, gidx(z, y0 + y, x0 + x), make_float2(rv[j].x - w0[j] - av[j].x * k0[j],
+                                                       rv[j].y - w1[j] - av[j].y * k1[j]));
         }
       }
       __syncthreads();

@@ -43,8 +43,8 @@ struct SGeo {
 // Direct global-to-LDS copy of 16 bytes per lane: lane l of the wave writes
 // lds_wave + 16 l (lds_wave the same in every lane); inactive lanes write
 // nothing.  Completion is counted by vmcnt of the issuing wave.
-__device__ __forceinline__ void slds_copy16(const void* g, void* lds_wave) {
-  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
+__device__ __forceinline__ void slds_copy16(gptr<const unsigned char> g, void* lds_wave) {
+  __builtin_amdgcn_global_load_lds((gptr<void>)g, (__attribute__((address_space(3))) void*)lds_wave, 16, 0, 0);
 }
 
 // One phase: for the region's row tiles (16 consecutive region nodes each,
@@ -56,7 +56,7 @@ __device__ __forceinline__ void slds_copy16(const void* g, void* lds_wave) {
 // (chunk vector idx at byte 16 idx) and copied straight from global memory.
 template <bool BF, int NCT, int NACC, int GR, class Pre, class Epi>
 __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src, int srcW, int dstW,
-                                       int ndst, const void* w0, const void* w1,
+                                       int ndst, gptr<const unsigned char> w0, gptr<const unsigned char> w1,
                                        unsigned char* wbuf, int kc, Pre pre, Epi epi) {
   constexpr int KV = BF ? 8 : 1, ES = BF ? 2 : 4;
   constexpr int BROW = NCT * 16 * KV;           // elements of one pair row of the weights
@@ -117,7 +117,7 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
           if (idx < total) {
             const int a = idx / (4 * ks * V16), rem = idx % (4 * ks * V16);
             const int row = rem / V16, vv = rem % V16;
-            slds_copy16(reinterpret_cast<const unsigned char*>(a ? w1 : w0) +
+            slds_copy16((a ? w1 : w0) +
                             ((size_t)(4 * s0 + row) * ncols * KV) * ES + (size_t)vv * 16,
                         wbuf + (size_t)__builtin_amdgcn_readfirstlane(base) * 16);
           }
@@ -210,6 +210,9 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
   unsigned char* b02 = smem;
   unsigned char* b1 = smem + (rbytes(G::N0) > rbytes(G::N2) ? rbytes(G::N0) : rbytes(G::N2));
   unsigned char* wbuf = b1 + rbytes(G::N1);
+  const gptr<const float> gr = to_global<const float>(A.r), ga = to_global<const float>(A.a);
+  const gptr<const float> gs = to_global<const float>(A.s), ge = to_global<const float>(A.e);
+  const gptr<float> geo = to_global<float>(A.eo);
   auto inside = [&](int y, int x) { return x >= 0 && x < NX && y >= 0 && y < NY; };
   auto put = [&](unsigned char* buf, int node, int c, float v) {
     if constexpr (BF) reinterpret_cast<unsigned short*>(buf)[(size_t)node * stride + c] = sf2bf(v);
@@ -217,7 +220,7 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
   };
   // stage a FP32 field [nodes][C] on a region of width W, height H, halo h;
   // loads are issued in batches of SB per thread before any LDS store
-  auto stage = [&](unsigned char* buf, const float* __restrict__ f, int W, int H, int h) {
+  auto stage = [&](unsigned char* buf, gptr<const float> f, int W, int H, int h) {
     constexpr int SB = 8;
     const int ng = cinp / 4;
     const int total = W * H * ng;
@@ -233,8 +236,8 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
         const int hy = node / W, hx = node - hy * W;
         const int gy = y0 - h + hy, gx = x0 - h + hx;
         if (inside(gy, gx) && c < C) {
-          const float* p = f + ((size_t)gy * NX + gx) * C + c;
-          if (vec4) v[k] = *reinterpret_cast<const float4*>(p);
+          const gptr<const float> p = f + ((size_t)gy * NX + gx) * C + c;
+          if (vec4) v[k] = gld((gptr<const float4>)p, 0);
           else {
             v[k].x = p[0];
             if (c + 1 < C) v[k].y = p[1];
@@ -265,18 +268,18 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
 
   // ---- phase 1: t on R1 (FIRST: t = r)
   if (VAR == L1_FIRST) {
-    stage(b1, A.r, G::W1, G::H1, 2);
+    stage(b1, gr, G::W1, G::H1, 2);
   } else {
-    stage(b02, A.e, G::W0, G::H0, 3);
+    stage(b02, ge, G::W0, G::H0, 3);
     // (the chunk loop's first barrier orders the staging before any read)
-    sphase<BF, NCT, 2, GR1>(A, b02, G::W0, G::W1, G::N1, A.wW, A.wKA, wbuf, A.kc1,
+    sphase<BF, NCT, 2, GR1>(A, b02, G::W0, G::W1, G::N1, to_global<const unsigned char>(A.wW), to_global<const unsigned char>(A.wKA), wbuf, A.kc1,
         [&](int n, int c) {
           const int hy = n / G::W1, hx = n - hy * G::W1;
           const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
           float2 v = make_float2(0.f, 0.f);
           if (c < C && inside(gy, gx)) {
             const size_t o = ((size_t)gy * NX + gx) * C + c;
-            v = make_float2(A.r[o], A.a[o]);
+            v = make_float2(gr[o], ga[o]);
           }
           return v;
         },
@@ -291,12 +294,12 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
   }
   __syncthreads();
   // ---- phase 2: u = s (.) (KS * t) on R2 (into the R0 storage)
-  sphase<BF, NCT, 1, GR2>(A, b1, G::W1, G::W2, G::N2, A.wKS, nullptr, wbuf, A.kc2,
+  sphase<BF, NCT, 1, GR2>(A, b1, G::W1, G::W2, G::N2, to_global<const unsigned char>(A.wKS), nullptr, wbuf, A.kc2,
       [&](int n, int c) {
         const int hy = n / G::W2, hx = n - hy * G::W2;
         const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
         float2 v = make_float2(0.f, 0.f);
-        if (c < C && inside(gy, gx)) v.x = A.s[((size_t)gy * NX + gx) * C + c];
+        if (c < C && inside(gy, gx)) v.x = gs[((size_t)gy * NX + gx) * C + c];
         return v;
       },
       [&](int n, int c, float acc, float, float2 sv) {
@@ -309,12 +312,12 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
       });
   __syncthreads();
   // ---- phase 3: e' = e + Wsm * u on the tile
-  sphase<BF, NCT, 1, GR2>(A, b02, G::W2, G::TX, G::N3, A.wSM, nullptr, wbuf, A.kc2,
+  sphase<BF, NCT, 1, GR2>(A, b02, G::W2, G::TX, G::N3, to_global<const unsigned char>(A.wSM), nullptr, wbuf, A.kc2,
       [&](int n, int c) {
         const int hy = n / G::TX, hx = n - hy * G::TX;
         const int gy = y0 + hy, gx = x0 + hx;
         float2 v = make_float2(0.f, 0.f);
-        if (VAR != L1_FIRST && c < C && inside(gy, gx)) v.x = A.e[((size_t)gy * NX + gx) * C + c];
+        if (VAR != L1_FIRST && c < C && inside(gy, gx)) v.x = ge[((size_t)gy * NX + gx) * C + c];
         return v;
       },
       [&](int n, int c, float acc, float, float2 ev) {
@@ -322,7 +325,7 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
         const int gy = y0 + hy, gx = x0 + hx;
         if (c >= C || !inside(gy, gx)) return;
         const size_t o = ((size_t)gy * NX + gx) * C + c;
-        A.eo[o] = (VAR == L1_FIRST) ? acc : ev.x + acc;
+        geo[o] = (VAR == L1_FIRST) ? acc : ev.x + acc;
       });
 }
 
