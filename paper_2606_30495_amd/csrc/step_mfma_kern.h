@@ -50,11 +50,11 @@ __device__ __forceinline__ void slds_copy16(gptr<const unsigned char> g, void* l
 // One phase: for the region's row tiles (16 consecutive region nodes each,
 // split over the 4 waves in groups of GR), acc[a] = sum over K of
 // A(src region, tap offsets) x B(weights of tensor a); then `epi` stores
-// the results.  The global operands of the epilogue are fetched by `pre`
-// before the group's K loop, so their latency overlaps it.  Weights stream
+// the results.  The global operands of the epilogue are fetched by `pre`,
+// before the group's K loop when EARLY, so their latency overlaps it.  Weights stream
 // through LDS in chunks of up to `kc` K-steps, laid out [a][4 ks rows][BROW]
 // (chunk vector idx at byte 16 idx) and copied straight from global memory.
-template <bool BF, int NCT, int NACC, int GR, class Pre, class Epi>
+template <bool BF, int NCT, int NACC, int GR, bool EARLY, class Pre, class Epi>
 __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src, int srcW, int dstW,
                                        int ndst, gptr<const unsigned char> w0, gptr<const unsigned char> w1,
                                        unsigned char* wbuf, int kc, Pre pre, Epi epi) {
@@ -96,17 +96,22 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
     for (int i = 0; i < GR; ++i) sbase[i] = snode[i] * stride;
     PairWalk pw;
     pw.init(lg, cpv, npairs);
-    // epilogue operands: lane (li, lg) holds rows 4 lg + rr of each tile, column li
+    // epilogue operands: lane (li, lg) holds rows 4 lg + rr of each tile,
+    // column li; fetched before the K loop when EARLY (latency hidden behind
+    // it), else after it (fewer registers live across the loop)
     float2 ops[GR][NCT][4];
+    auto fetch_ops = [&]() {
 #pragma unroll
-    for (int i = 0; i < GR; ++i)
+      for (int i = 0; i < GR; ++i)
 #pragma unroll
-      for (int t = 0; t < NCT; ++t)
+        for (int t = 0; t < NCT; ++t)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          const int n = (wave + 4 * (g * GR + i)) * 16 + 4 * lg + rr;
-          ops[i][t][rr] = (live[i] && n < ndst) ? pre(n, t * 16 + li) : make_float2(0.f, 0.f);
-        }
+          for (int rr = 0; rr < 4; ++rr) {
+            const int n = (wave + 4 * (g * GR + i)) * 16 + 4 * lg + rr;
+            ops[i][t][rr] = (live[i] && n < ndst) ? pre(n, t * 16 + li) : make_float2(0.f, 0.f);
+          }
+    };
+    if constexpr (EARLY) fetch_ops();
     for (int s0 = 0; s0 < nsteps; s0 += kc) {
       const int ks = (nsteps - s0) < kc ? (nsteps - s0) : kc;
       if (!resident || (g == 0 && s0 == 0)) {
@@ -127,9 +132,6 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
       }
       // Row tiles past the region (live false) are computed on a clamped,
       // valid node and discarded, so no branch splits a step's LDS reads.
-      // The fragments of step ss + 1 are read before the products of step ss
-      // are issued (two register sets), so LDS latency overlaps the matrix
-      // cores; every accumulator still takes the steps in order.
       typedef typename std::conditional<BF, sbf16x8, float>::type Frag;
       // steps are loaded in order, so the pair walk advances once per call
       auto load = [&](int ss, Frag (&bfr)[NACC][NCT], Frag (&af)[GR]) {
@@ -163,17 +165,13 @@ __device__ __forceinline__ void sphase(const SArgs& A, const unsigned char* src,
               else acc[a][i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[a][t], acc[a][i][t], 0, 0, 0);
             }
       };
-      Frag b0[NACC][NCT], a0[GR], b1[NACC][NCT], a1[GR];
-      load(0, b0, a0);
-      int ss = 0;
-      for (; ss + 1 < ks; ss += 2) {
-        load(ss + 1, b1, a1);
+      Frag b0[NACC][NCT], a0[GR];
+      for (int ss = 0; ss < ks; ++ss) {
+        load(ss, b0, a0);
         mma(b0, a0);
-        if (ss + 2 < ks) load(ss + 2, b0, a0);
-        mma(b1, a1);
       }
-      if (ss < ks) mma(b0, a0);
     }
+    if constexpr (!EARLY) fetch_ops();
 #pragma unroll
     for (int i = 0; i < GR; ++i) {
       if (!live[i]) continue;
@@ -263,8 +261,18 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
       }
     }
   };
-  constexpr int GR1 = (8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1;
-  constexpr int GR2 = (8 / NCT) > 0 ? 8 / NCT : 1;
+  // row tiles per group of a phase: the register budget (8 accumulator
+  // tiles per wave), but no more than a wave's share of the region's tiles
+  constexpr int CAP1 = (8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1;
+  constexpr int CAP2 = (8 / NCT) > 0 ? 8 / NCT : 1;
+  constexpr int PW1 = ((G::N1 + 15) / 16 + 3) / 4, PW2 = ((G::N2 + 15) / 16 + 3) / 4;
+  constexpr int PW3 = ((G::N3 + 15) / 16 + 3) / 4;
+  constexpr int GR1 = CAP1 < PW1 ? CAP1 : PW1;
+  constexpr int GR2 = CAP2 < PW2 ? CAP2 : PW2;
+  constexpr int GR3 = CAP2 < PW3 ? CAP2 : PW3;
+  // narrow channel counts have many small blocks, where occupancy counts
+  // more than the epilogue latency of one block
+  constexpr bool EARLY = NCT >= 2;
 
   // ---- phase 1: t on R1 (FIRST: t = r)
   if (VAR == L1_FIRST) {
@@ -272,7 +280,7 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
   } else {
     stage(b02, ge, G::W0, G::H0, 3);
     // (the chunk loop's first barrier orders the staging before any read)
-    sphase<BF, NCT, 2, GR1>(A, b02, G::W0, G::W1, G::N1, to_global<const unsigned char>(A.wW), to_global<const unsigned char>(A.wKA), wbuf, A.kc1,
+    sphase<BF, NCT, 2, GR1, EARLY>(A, b02, G::W0, G::W1, G::N1, to_global<const unsigned char>(A.wW), to_global<const unsigned char>(A.wKA), wbuf, A.kc1,
         [&](int n, int c) {
           const int hy = n / G::W1, hx = n - hy * G::W1;
           const int gy = y0 - 2 + hy, gx = x0 - 2 + hx;
@@ -294,7 +302,7 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
   }
   __syncthreads();
   // ---- phase 2: u = s (.) (KS * t) on R2 (into the R0 storage)
-  sphase<BF, NCT, 1, GR2>(A, b1, G::W1, G::W2, G::N2, to_global<const unsigned char>(A.wKS), nullptr, wbuf, A.kc2,
+  sphase<BF, NCT, 1, GR2, EARLY>(A, b1, G::W1, G::W2, G::N2, to_global<const unsigned char>(A.wKS), nullptr, wbuf, A.kc2,
       [&](int n, int c) {
         const int hy = n / G::W2, hx = n - hy * G::W2;
         const int gy = y0 - 1 + hy, gx = x0 - 1 + hx;
@@ -312,7 +320,7 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
       });
   __syncthreads();
   // ---- phase 3: e' = e + Wsm * u on the tile
-  sphase<BF, NCT, 1, GR2>(A, b02, G::W2, G::TX, G::N3, to_global<const unsigned char>(A.wSM), nullptr, wbuf, A.kc2,
+  sphase<BF, NCT, 1, GR3, EARLY>(A, b02, G::W2, G::TX, G::N3, to_global<const unsigned char>(A.wSM), nullptr, wbuf, A.kc2,
       [&](int n, int c) {
         const int hy = n / G::TX, hx = n - hy * G::TX;
         const int gy = y0 + hy, gx = x0 + hx;
