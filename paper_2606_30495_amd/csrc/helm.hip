@@ -190,36 +190,39 @@ __global__ __launch_bounds__(HB) void helm_kernel(HArgs A, int nb) {
   helm_body<D, TIN, MODE>(A, t);
 }
 
-// 3D plain A u without the residual form: a block owns an MX x MY column of
-// nodes and walks MZ planes in z.  Each thread keeps u at z - 1, z and z + 1
-// in registers, so the z neighbours and the z coefficients are read once per
-// plane; its x and y coefficients are loaded once.  The loads of the next
-// plane (u two planes ahead, the four in-plane neighbours, k^2) are issued
-// before the current plane is computed, so their latency overlaps the work.
-// Six loads per node instead of fourteen; node_op gives the same bits as the
+// 3D plain A u without the residual form: a block owns MC consecutive
+// columns of the flattened (y, x) plane (no thread falls outside the grid at
+// the x edge: 64 x 4 tiles left 16% idle at 216 nodes per row) and walks MZ
+// planes in z.  Each thread keeps u at z - 1, z and z + 1 in registers, so
+// the z neighbours and the z coefficients are read once per plane; its x
+// and y coefficients are loaded once.  The loads of the next plane (u two
+// planes ahead, the four in-plane neighbours, k^2) are issued before the
+// current plane is computed, so their latency overlaps the work.  Six loads
+// per node instead of fourteen; node_op gives the same bits as the
 // block-linear kernel.
-constexpr int MX = 64, MY = 4, MZ = 16;
+constexpr int MC = 256, MZ = 16;
 
 int march_tiles(const Dims& n) {
-  return ((n.n[2] + MX - 1) / MX) * ((n.n[1] + MY - 1) / MY) * ((n.n[0] + MZ - 1) / MZ);
+  const long long plane = (long long)n.n[1] * n.n[2];
+  return (int)((plane + MC - 1) / MC) * ((n.n[0] + MZ - 1) / MZ);
 }
 
 template <typename TIN>
-__global__ __launch_bounds__(MX * MY) void helm_march_kernel(HArgs A, int ntiles) {
+__global__ __launch_bounds__(MC) void helm_march_kernel(HArgs A, int ntiles) {
   const TIN* __restrict__ u = reinterpret_cast<const TIN*>(A.u);
-  double2* __restrict__ out = reinterpret_cast<double2*>(A.out);
+  const gptr<double> __restrict__ out = to_global<double>(A.out);
   const gptr<const double> __restrict__ k2 = to_global<const double>(A.op.k2);
   const int NZ = A.op.ext.n[0], NY = A.op.ext.n[1], NX = A.op.ext.n[2];
   const int per = (ntiles + 7) / 8;
   const int tl = (blockIdx.x % 8) * per + blockIdx.x / 8;   // XCD-contiguous bands
   if (tl >= ntiles) return;
-  const int tx = (NX + MX - 1) / MX, ty = (NY + MY - 1) / MY;
-  const int x0 = (tl % tx) * MX, y0 = ((tl / tx) % ty) * MY, z0 = (tl / (tx * ty)) * MZ;
-  const int ze = min(z0 + MZ, NZ);
-  const int gx = x0 + (int)(threadIdx.x % MX), gy = y0 + (int)(threadIdx.x / MX);
-  if (gx >= NX || gy >= NY) return;   // no barriers below
   const long long plane = (long long)NY * NX;
-  const long long col = (long long)gy * NX + gx;
+  const int tc = (int)((plane + MC - 1) / MC);
+  const int z0 = (tl / tc) * MZ;
+  const long long col = (long long)(tl % tc) * MC + threadIdx.x;
+  if (col >= plane) return;   // no barriers below
+  const int gy = (int)(col / NX), gx = (int)(col - (long long)gy * NX);
+  const int ze = min(z0 + MZ, NZ);
   const bool hxm = gx > 0, hxp = gx < NX - 1, hym = gy > 0, hyp = gy < NY - 1;
   const long long oxm = hxm ? -1 : 0, oxp = hxp ? 1 : 0;
   const long long oym = hym ? -(long long)NX : 0, oyp = hyp ? (long long)NX : 0;
@@ -269,7 +272,7 @@ __global__ __launch_bounds__(MX * MY) void helm_march_kernel(HArgs A, int ntiles
       gs += g2;
     }
     const cplx acc = node_op<3>(uc, kk, gs, A.op.gmax, m, pc, m, pc, um, up);
-    out[(long long)z * plane + col] = make_double2(acc.re, acc.im);
+    ((gptr<nvd2>)out)[(long long)z * plane + col] = nvd2{acc.re, acc.im};
     ucm = uc; uc = ucp; ucp = ucp2;
     nb[0] = nb2[0]; nb[1] = nb2[1]; nb[2] = nb2[2]; nb[3] = nb2[3];
     kk = kk2;
@@ -303,8 +306,8 @@ hipError_t helm_dispatch(int dim, int tin, const HArgs* A, int nb, const BatchLa
     if (dim == 3 && mode == 0 && !A->f && !A->partial) {
       const int nt = march_tiles(A->op.ext);
       const unsigned gm = (unsigned)((nt + 7) / 8 * 8);
-      if (tin == T_F64) hipLaunchKernelGGL((helm_march_kernel<double>), dim3(gm), dim3(MX * MY), 0, s, *A, nt);
-      else hipLaunchKernelGGL((helm_march_kernel<float>), dim3(gm), dim3(MX * MY), 0, s, *A, nt);
+      if (tin == T_F64) hipLaunchKernelGGL((helm_march_kernel<double>), dim3(gm), dim3(MC), 0, s, *A, nt);
+      else hipLaunchKernelGGL((helm_march_kernel<float>), dim3(gm), dim3(MC), 0, s, *A, nt);
       return hipGetLastError();
     }
     const unsigned g = (unsigned)((nb + 7) / 8 * 8);
