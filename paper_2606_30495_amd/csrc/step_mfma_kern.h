@@ -262,8 +262,10 @@ __device__ __forceinline__ void mstep_body(const SArgs& A, const int vblk) {
     }
   };
   // row tiles per group of a phase: the register budget (8 accumulator
-  // tiles per wave), but no more than a wave's share of the region's tiles
-  constexpr int CAP1 = (8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1;
+  // tiles per wave; 12 for phase 1 at 32 channels, whose few blocks all fit
+  // on the chip at once, so that its wave share of three tiles is one
+  // group), but no more than a wave's share of the region's tiles
+  constexpr int CAP1 = NCT == 2 ? 3 : ((8 / (2 * NCT)) > 0 ? 8 / (2 * NCT) : 1);
   constexpr int CAP2 = (8 / NCT) > 0 ? 8 / NCT : 1;
   constexpr int PW1 = ((G::N1 + 15) / 16 + 3) / 4, PW2 = ((G::N2 + 15) / 16 + 3) / 4;
   constexpr int PW3 = ((G::N3 + 15) / 16 + 3) / 4;
