@@ -73,8 +73,9 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   constexpr int TYt = TY + 2 * TG, TXt = TX + 2 * TG, NT = TYt * TXt;
   constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
   constexpr int NO = TY * TX;
-  constexpr int RP = 4;                                   // points per thread per phase
-  static_assert(NT <= NTH * RP && NU <= NTH * RP && NO <= NTH * RP, "one round per phase");
+  // points per thread in each phase: just enough slots for the phase's box
+  // (every slot costs the full tap loop, used or not)
+  constexpr int RT = (NT + NTH - 1) / NTH, RU = (NU + NTH - 1) / NTH, RO = (NO + NTH - 1) / NTH;
   constexpr int PE = (NE + NTH - 1) / NTH;                // staged e values per thread
   // LDS: `sa` holds e (halo H), then u (halo 1) once t exists; `sb` holds t.
   constexpr int NA = (VAR == L1_FIRST) ? NU : (VAR == L1_RESID ? NE : (NE > NU ? NE : NU));
@@ -94,7 +95,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
   // ---- every global operand of the block is requested up front, so the
   // block waits for one memory latency instead of one per phase: e with
   // halo H (staged in LDS), r and a on the t box, s on the u box, e on the
-  // tile.  A thread owns the same RP points of each box throughout.
+  // tile.  A thread owns the same points of each box throughout.
   float2 v[PE];
   if (VAR != L1_FIRST) {
 #pragma unroll
@@ -104,11 +105,11 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
       v[k] = ldz(e, gidx(y0 - H + y, x0 - H + x), i < NE && inside(y0 - H + y, x0 - H + x));
     }
   }
-  float2 rv[RP], av[RP];
-  int eb[RP];
-  bool okt[RP];
+  float2 rv[RT], av[RT];
+  int eb[RT];
+  bool okt[RT];
 #pragma unroll
-  for (int k = 0; k < RP; ++k) {
+  for (int k = 0; k < RT; ++k) {
     const int i = threadIdx.x + k * NTH;
     const int y = i / TXt, x = i % TXt;
     const int gy = y0 - TG + y, gx = x0 - TG + x;
@@ -117,12 +118,12 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
     av[k] = (VAR != L1_FIRST) ? ldz(a, gidx(gy, gx), okt[k]) : zero;
     eb[k] = (i < NT) ? (y + H - TG) * EX + (x + H - TG) : EX + 1;
   }
-  float2 sv[RP], ev[RP];
-  int tb[RP], ub[RP];
-  bool oku[RP], oko[RP];
+  float2 sv[RU], ev[RO];
+  int tb[RU], ub[RO];
+  bool oku[RU], oko[RO];
   if (VAR != L1_RESID) {
 #pragma unroll
-    for (int k = 0; k < RP; ++k) {
+    for (int k = 0; k < RU; ++k) {
       const int i = threadIdx.x + k * NTH;
       const int y = i / UX, x = i % UX;
       const int gy = y0 - 1 + y, gx = x0 - 1 + x;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
       tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
     }
 #pragma unroll
-    for (int k = 0; k < RP; ++k) {
+    for (int k = 0; k < RO; ++k) {
       const int i = threadIdx.x + k * NTH;
       const int y = i / TX, x = i % TX;
       oko[k] = i < NO && inside(y0 + y, x0 + x);
@@ -150,9 +151,9 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
 
   // ---- t box: t = r - (W*e + a (.) (KA*e)) (FIRST: t = r; RESID: to memory)
   {
-    float w0[RP], w1[RP], k0[RP], k1[RP];
+    float w0[RT], w1[RT], k0[RT], k1[RT];
 #pragma unroll
-    for (int k = 0; k < RP; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
+    for (int k = 0; k < RT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
     if (VAR != L1_FIRST) {
 #pragma unroll
       for (int t = 0; t < 9; ++t) {
@@ -160,7 +161,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
         const float a00 = W_(w.W[0][0][t]), a01 = W_(w.W[0][1][t]), a10 = W_(w.W[1][0][t]), a11 = W_(w.W[1][1][t]);
         const float b00 = W_(w.KA[0][0][t]), b01 = W_(w.KA[0][1][t]), b10 = W_(w.KA[1][0][t]), b11 = W_(w.KA[1][1][t]);
 #pragma unroll
-        for (int k = 0; k < RP; ++k) {
+        for (int k = 0; k < RT; ++k) {
           const float2 q = sa[eb[k] + to];
           w0[k] = fmaf(a00, q.x, fmaf(a01, q.y, w0[k]));
           w1[k] = fmaf(a10, q.x, fmaf(a11, q.y, w1[k]));
@@ -170,7 +171,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
       }
     }
 #pragma unroll
-    for (int k = 0; k < RP; ++k) {
+    for (int k = 0; k < RT; ++k) {
       const int i = threadIdx.x + k * NTH;
       if (i >= NT) continue;
       const float2 tv = okt[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
@@ -187,15 +188,15 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
 
   // ---- u box: u = s (.) (KS * t), into the e storage (e is not read again)
   {
-    float c0[RP], c1[RP];
+    float c0[RU], c1[RU];
 #pragma unroll
-    for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
+    for (int k = 0; k < RU; ++k) c0[k] = c1[k] = 0.f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int to = (t / 3 - 1) * TXt + (t % 3 - 1);
       const float a00 = W_(w.KS[0][0][t]), a01 = W_(w.KS[0][1][t]), a10 = W_(w.KS[1][0][t]), a11 = W_(w.KS[1][1][t]);
 #pragma unroll
-      for (int k = 0; k < RP; ++k) {
+      for (int k = 0; k < RU; ++k) {
         const float2 q = sb[tb[k] + to];
         c0[k] = fmaf(a00, q.x, fmaf(a01, q.y, c0[k]));
         c1[k] = fmaf(a10, q.x, fmaf(a11, q.y, c1[k]));
@@ -203,7 +204,7 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
     }
     // every thread has finished reading e from sa (barrier above) before u lands there
 #pragma unroll
-    for (int k = 0; k < RP; ++k) {
+    for (int k = 0; k < RU; ++k) {
       const int i = threadIdx.x + k * NTH;
       if (i < NU) sa[i] = oku[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
     }
@@ -212,22 +213,22 @@ __device__ __forceinline__ void l1_body(const L1Args& A, const L1Weights& w, con
 
   // ---- output tile: e' = e + Wsm * u
   {
-    float c0[RP], c1[RP];
+    float c0[RO], c1[RO];
 #pragma unroll
-    for (int k = 0; k < RP; ++k) c0[k] = c1[k] = 0.f;
+    for (int k = 0; k < RO; ++k) c0[k] = c1[k] = 0.f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int to = (t / 3 - 1) * UX + (t % 3 - 1);
       const float a00 = W_(w.Wsm[0][0][t]), a01 = W_(w.Wsm[0][1][t]), a10 = W_(w.Wsm[1][0][t]), a11 = W_(w.Wsm[1][1][t]);
 #pragma unroll
-      for (int k = 0; k < RP; ++k) {
+      for (int k = 0; k < RO; ++k) {
         const float2 q = sa[ub[k] + to];
         c0[k] = fmaf(a00, q.x, fmaf(a01, q.y, c0[k]));
         c1[k] = fmaf(a10, q.x, fmaf(a11, q.y, c1[k]));
       }
     }
 #pragma unroll
-    for (int k = 0; k < RP; ++k) {
+    for (int k = 0; k < RO; ++k) {
       if (!oko[k]) continue;
       const int i = threadIdx.x + k * NTH;
       gst(eo, gidx(y0 + i / TX, x0 + i % TX), make_float2(ev[k].x + c0[k], ev[k].y + c1[k]));
