@@ -1,0 +1,154 @@
+"""GPU parity at the full benchmark sizes, in the configuration bench.py
+times: the 2D 1024^2 Gaussian-random-field workload (1056^2 extended,
+6 levels 2/8/16/32/64/64, FGMRES(30)) and the 3D 192^3 layered workload
+(216^3 extended, 5 levels 2/12/24/48/96, FGMRES(20)), random-init weights
+from the workload's seed.
+
+Where the FP64 oracle finishes in seconds at that size (the operator at
+both sizes, the 2D V-cycle and three 2D FGMRES iterations) the whole output
+is compared.  The 3D V-cycle takes the oracle minutes, so at 216^3 the
+checks are properties that hold at any size: linearity in r over the reals
+(Sec. 3.2), bitwise repeatability, zero in gives zero out, and the reported
+true residual of a solve equal to the oracle's FP64 recomputation from the
+returned iterate."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import helmholtz, krylov, mcmg
+from tests._gpu_common import rel_l2, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def _workload(name):
+    """Problem, weights and oracle parts of a benchmark workload (cached:
+    the oracle setup at 216^3 takes seconds)."""
+    if name not in _CACHE:
+        cfg = synth.CONFIGS[name]
+        c, omega, h, f = synth.make_problem(cfg)
+        tens = synth.make_weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, cfg.weight_seed)
+        blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
+        op = helmholtz.setup_operator(c, omega, h, cfg.npml)
+        _CACHE[name] = dict(cfg=cfg, c=c, omega=omega, h=h, f=f, tens=tens, blob=blob, op=op)
+    return _CACHE[name]
+
+
+def _handle(w, precision):
+    from paper_2606_30495_amd import Handle
+    cfg = w["cfg"]
+    return Handle(w["c"], w["omega"], w["h"], cfg.npml, w["blob"], precision=precision,
+                  restart=cfg.restart)
+
+
+def _preconditioner(w):
+    cfg = w["cfg"]
+    W = mcmg.Weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, w["tens"])
+    return mcmg.Preconditioner(W, np.sqrt(w["op"]["k2"]), w["h"])
+
+
+@pytest.mark.parametrize("name", ["grf1024", "layered192"])
+def test_fullsize_matvec_matches_oracle(name):
+    """A u in FP64 on the whole extended grid against the oracle's stencil."""
+    say(f"[full-matvec] {name}")
+    w = _workload(name)
+    H = _handle(w, "bf16")
+    u = synth.random_rhs(H.ext_shape, 11)
+    y = to_dev(np.zeros_like(u))
+    H.matvec(to_dev(u), y)
+    err = rel_l2(to_host(y), helmholtz.apply(w["op"], u))
+    H.close()
+    say(f"  relL2 = {err:.3e}")
+    assert err <= 1e-13, err
+
+
+def test_fullsize_vcycle_2d_matches_oracle():
+    """One V-cycle application at 1056^2 against the FP64 oracle: FP32 within
+    1e-5, BF16 within 2e-2 relative L2."""
+    say("[full-vcycle] grf1024")
+    w = _workload("grf1024")
+    M = _preconditioner(w)
+    r = synth.random_rhs(w["f"].shape, 12)
+    ref = M(r)
+    for precision, tol in (("fp32", 1e-5), ("bf16", 2e-2)):
+        H = _handle(w, precision)
+        z = to_dev(np.zeros_like(r))
+        H.apply(to_dev(r), z)
+        err = rel_l2(to_host(z), ref)
+        H.close()
+        say(f"  {precision} relL2 = {err:.3e}")
+        assert err <= tol, (precision, err)
+
+
+def test_fullsize_fgmres_2d_history_matches_oracle():
+    """Three FGMRES(30) iterations from u = 0 at 1056^2 (FP32 V-cycle): the
+    residual history and the returned iterate follow the oracle's."""
+    say("[full-fgmres] grf1024")
+    w = _workload("grf1024")
+    M = _preconditioner(w)
+    f = w["f"]
+    H = _handle(w, "fp32")
+    u = to_dev(np.zeros_like(f))
+    info = H.solve(to_dev(f), u, tol=1e-6, maxit=3)
+    ug = to_host(u)
+    H.close()
+    uo, io = krylov.fgmres(lambda x: helmholtz.apply(w["op"], x), M, f, m=30, tol=1e-6, maxit=3)
+    hg, ho = np.array(info["hist"]), np.array(io["hist"])
+    say(f"  gpu {hg}; oracle {ho}")
+    assert info["iters"] == io["iters"] == 3
+    assert np.max(np.abs(hg - ho) / ho) < 1e-5
+    assert rel_l2(ug, uo) < 1e-4
+    true = np.linalg.norm(f - helmholtz.apply(w["op"], ug)) / np.linalg.norm(f)
+    assert abs(info["relres_true"] - true) <= 1e-10 * true
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_fullsize_vcycle_3d_properties(precision):
+    """At 216^3: the V-cycle is linear in r over the reals to the precision's
+    rounding level, repeats bitwise, and maps zero to zero."""
+    say(f"[full-vcycle-props] layered192 {precision}")
+    w = _workload("layered192")
+    H = _handle(w, precision)
+    shape = H.ext_shape
+    r1 = synth.random_rhs(shape, 21)
+    r2 = synth.random_rhs(shape, 22)
+    outs = []
+    for r in (r1, r2, 0.7 * r1 - 1.9 * r2, r1):
+        z = to_dev(np.zeros_like(r))
+        H.apply(to_dev(r), z)
+        outs.append(to_host(z))
+    z0 = to_dev(np.zeros_like(r1))
+    H.apply(to_dev(np.zeros_like(r1)), z0)
+    zero_out = to_host(z0)
+    H.close()
+    lin = rel_l2(outs[2], 0.7 * outs[0] - 1.9 * outs[1])
+    say(f"  linearity relL2 = {lin:.3e}")
+    # bf16 rounds each operand to 8 bits, so the sum of two inputs rounds
+    # differently from the inputs apart
+    assert lin <= (1e-5 if precision == "fp32" else 1e-2), lin
+    assert np.array_equal(outs[0], outs[3])
+    assert np.all(zero_out == 0)
+    assert np.all(np.isfinite(outs[0])) and np.linalg.norm(outs[0]) > 0
+
+
+def test_fullsize_fgmres_3d_true_residual():
+    """Three FGMRES(20) iterations at 216^3 (BF16 V-cycle, FP64 outer loop):
+    the reported true residual equals the oracle's FP64 recomputation
+    |f - A u| / |f| from the returned iterate, and the residual history does
+    not increase."""
+    say("[full-fgmres] layered192")
+    w = _workload("layered192")
+    f = w["f"]
+    H = _handle(w, "bf16")
+    u = to_dev(np.zeros_like(f))
+    info = H.solve(to_dev(f), u, tol=1e-6, maxit=3)
+    ug = to_host(u)
+    H.close()
+    true = np.linalg.norm(f - helmholtz.apply(w["op"], ug)) / np.linalg.norm(f)
+    hist = np.array(info["hist"])
+    say(f"  reported {info['relres_true']:.6e}, oracle {true:.6e}; hist {hist}")
+    assert info["iters"] == 3
+    assert abs(info["relres_true"] - true) <= 1e-10 * true
+    assert np.all(np.diff(hist) <= 1e-12 * hist[0])
