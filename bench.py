@@ -78,6 +78,24 @@ def roofline_for(rec, precision):
             "frac": round(ach / peak_fl, 4), "traffic": None}
 
 
+def mfma_for(recs, precision, ms_per_step, iters):
+    """Matrix-core utilisation of the V-cycle convolutions: the algorithmic
+    flops (2 per MAC) of every matrix-core launch of the profiled solve
+    (implicit-GEMM convolutions and fused steps) over their summed
+    event-timed durations, against the dense peak of the operand type."""
+    mm = [r for r in recs if r["name"].startswith(("mconv_kernel", "mstep_kernel"))]
+    fl = sum(r["flops_per_launch"] * r["launches"] for r in mm)
+    ms = sum(r["total_ms"] for r in mm)
+    if not mm or ms <= 0:
+        return None
+    peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP32_TFLOPS
+    ach = fl / (ms * 1e-3) / 1e12
+    return {"kernels": "matrix-core convolutions (mconv_kernel, mstep_kernel)",
+            "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
+            "ms_per_step": round(ms / max(iters, 1), 4),
+            "share_of_step": round(ms / max(iters, 1) / ms_per_step, 3)}
+
+
 def run_leg(cfg, c, omega, h, f, blob, precision, steps, warmup):
     """Setup, warm up, then time one solve of `steps` iterations from u = 0;
     repeat it with per-launch HIP-event timing for the kernel breakdown."""
@@ -522,6 +540,7 @@ def main():
         "solve": {"iters": head["iters"], "relres_true": head["info"]["relres_true"],
                   "converged": head["info"]["converged"], "setup_ms": round(head["setup_ms"], 2)},
         "roofline": roof,
+        "mfma": mfma_for(recs, a.precision, head["ms_per_step"], head["iters"]),
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                     for r in recs[:16]],
     }
