@@ -40,12 +40,40 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Block sums of NV values at once, each in block_sum's order (wave tree,
+// then the waves in order), with one pair of barriers for all of them;
+// results valid in thread 0.  sh must hold NV * RB/64 doubles.
+template <int NV>
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sh[k * (RB / 64) + wv] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < RB / 64; ++i) t += sh[k * (RB / 64) + i];
+      v[k] = t;
+    }
+  }
+}
+
+// Vectors per batch of the multi-dot: the loads of VB basis vectors are in
+// flight together and their 2 VB sums share one pair of barriers.
+constexpr int VB = 4;
+
 __device__ __forceinline__ void multidot_body(const double* __restrict__ V_, long long ldv, int nvec,
                                               const double* __restrict__ w_, long long n,
                                               double* __restrict__ partial_, int nb, int vblk) {
   const gptr<const double> V = to_global<const double>(V_), w = to_global<const double>(w_);
   const gptr<double> partial = to_global<double>(partial_);
-  __shared__ double sh[RB / 64];
+  __shared__ double sh[2 * VB * (RB / 64)];
   const long long base = (long long)vblk * RB * RPT;
   double wr[RPT], wi[RPT];
 #pragma unroll
@@ -54,32 +82,54 @@ __device__ __forceinline__ void multidot_body(const double* __restrict__ V_, lon
     if (p < n) { wr[q] = w[2 * p]; wi[q] = w[2 * p + 1]; }
     else { wr[q] = 0.0; wi[q] = 0.0; }
   }
-  for (int i = 0; i < nvec; ++i) {
-    const gptr<const double> v = V + (long long)i * 2 * ldv;
-    double sr = 0.0, si = 0.0;
+  for (int i0 = 0; i0 < nvec; i0 += VB) {
+    // all loads of the batch first (vectors past nvec and points past n
+    // read valid entries and are discarded), then the sums
+    double vr[VB][RPT], vi[VB][RPT];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const long long p = base + (long long)q * RB + threadIdx.x;
-      if (p < n) {
-        const double vr = v[2 * p], vi = v[2 * p + 1];
-        // conj(v) * w
-        sr += vr * wr[q] + vi * wi[q];
-        si += vr * wi[q] - vi * wr[q];
+    for (int k = 0; k < VB; ++k) {
+      const gptr<const double> v = V + (long long)(i0 + k < nvec ? i0 + k : 0) * 2 * ldv;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const long long p = base + (long long)q * RB + threadIdx.x;
+        const long long pc = p < n ? p : 0;
+        vr[k][q] = v[2 * pc];
+        vi[k][q] = v[2 * pc + 1];
       }
     }
-    const double tr = block_sum(sr, sh);
-    const double ti = block_sum(si, sh);
+    double acc[2 * VB];
+#pragma unroll
+    for (int k = 0; k < VB; ++k) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        const long long p = base + (long long)q * RB + threadIdx.x;
+        if (p < n) {
+          // conj(v) * w
+          sr += vr[k][q] * wr[q] + vi[k][q] * wi[q];
+          si += vr[k][q] * wi[q] - vi[k][q] * wr[q];
+        }
+      }
+      acc[2 * k] = sr;
+      acc[2 * k + 1] = si;
+    }
+    block_sums<2 * VB>(acc, sh);
     if (threadIdx.x == 0) {
-      partial[2 * ((long long)i * nb + vblk)] = tr;
-      partial[2 * ((long long)i * nb + vblk) + 1] = ti;
+#pragma unroll
+      for (int k = 0; k < VB; ++k) {
+        if (i0 + k >= nvec) break;
+        partial[2 * ((long long)(i0 + k) * nb + vblk)] = acc[2 * k];
+        partial[2 * ((long long)(i0 + k) * nb + vblk) + 1] = acc[2 * k + 1];
+      }
     }
   }
   double s2 = 0.0;
 #pragma unroll
   for (int q = 0; q < RPT; ++q) s2 += wr[q] * wr[q] + wi[q] * wi[q];
-  const double t2 = block_sum(s2, sh);
+  double t2[1] = {s2};
+  block_sums<1>(t2, sh);
   if (threadIdx.x == 0) {
-    partial[2 * ((long long)nvec * nb + vblk)] = t2;
+    partial[2 * ((long long)nvec * nb + vblk)] = t2[0];
     partial[2 * ((long long)nvec * nb + vblk) + 1] = 0.0;
   }
 }
@@ -115,22 +165,45 @@ __device__ __forceinline__ void update_body(const double* __restrict__ V_, long 
   const gptr<double> w = to_global<double>(w_), partial = to_global<double>(partial_);
   __shared__ double sh[RB / 64];
   const long long base = (long long)vblk * RB * RPT;
-  double s2 = 0.0;
+  double ar[RPT], ai[RPT];
+  bool ok[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const long long p = base + (long long)q * RB + threadIdx.x;
-    if (p >= n) break;
-    double ar = w[2 * p], ai = w[2 * p + 1];
-    for (int i = 0; i < nvec; ++i) {
-      const double cr = coef[2 * i], ci = coef[2 * i + 1];
-      const gptr<const double> v = V + (long long)i * 2 * ldv;
-      const double vr = v[2 * p], vi = v[2 * p + 1];
-      ar -= cr * vr - ci * vi;
-      ai -= cr * vi + ci * vr;
+    ok[q] = p < n;
+    ar[q] = ok[q] ? w[2 * p] : 0.0;
+    ai[q] = ok[q] ? w[2 * p + 1] : 0.0;
+  }
+  // vector-outer, so the loads of all the thread's points (and, unrolled,
+  // of two vectors) are in flight together; each point still sums over i in
+  // order
+#pragma unroll 2
+  for (int i = 0; i < nvec; ++i) {
+    const double cr = coef[2 * i], ci = coef[2 * i + 1];
+    const gptr<const double> v = V + (long long)i * 2 * ldv;
+    // points past n read entry 0 and are never stored (no branch splits
+    // the loads); all loads first, then the updates
+    double vr[RPT], vi[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const long long p = ok[q] ? base + (long long)q * RB + threadIdx.x : 0;
+      vr[q] = v[2 * p];
+      vi[q] = v[2 * p + 1];
     }
-    w[2 * p] = ar;
-    w[2 * p + 1] = ai;
-    s2 += ar * ar + ai * ai;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      ar[q] -= cr * vr[q] - ci * vi[q];
+      ai[q] -= cr * vi[q] + ci * vr[q];
+    }
+  }
+  double s2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    if (!ok[q]) continue;
+    const long long p = base + (long long)q * RB + threadIdx.x;
+    w[2 * p] = ar[q];
+    w[2 * p + 1] = ai[q];
+    s2 += ar[q] * ar[q] + ai[q] * ai[q];
   }
   const double t = block_sum(s2, sh);
   if (threadIdx.x == 0) partial[vblk] = t;
