@@ -5,6 +5,14 @@
         --cal-fetch <dir> --cal-write <dir> --cal-bytes B
         [--kernel NAME=SOURCE ...] [--src NAME_PREFIX=SOURCE ...]
 
+    python3 -m paper_2606_30495_amd.profsum mfma <dir> [prefix ...]
+
+`mfma` summarises a run with `--pmc MfmaUtil MfmaFlopsBF16` per kernel name
+(those starting with one of the prefixes, default mconv_kernel and
+mstep_kernel): dispatches, mean matrix-core flops per dispatch as counted
+by the hardware, mean dispatch duration, flops over duration, and
+MfmaUtil, the matrix-core busy cycles over the busy cycles of all SIMDs.
+
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 name, scales each by the calibration copy kernel's bytes-moved / counter
 ratio and prints a Markdown summary with a JSON block
@@ -113,7 +121,42 @@ def replay_run(trace, kernel):
             f"{sum(dur) / len(dur) / 1e3:.3f} us, mean start-to-start {span / len(best) / 1e3:.3f} us")
 
 
+def mfma(d, prefixes):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            k = short(r["Kernel_Name"])
+            if not k.startswith(tuple(prefixes)):
+                continue
+            e = per.setdefault(k, {})
+            disp = e.setdefault(r["Dispatch_Id"], {"dur": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+            disp[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = ["| kernel | dispatches | hw MFMA flops / dispatch | mean duration us | TFLOP/s (hw flops / duration) | MfmaUtil % |",
+           "|---|---|---|---|---|---|"]
+    tot_fl = tot_ns = 0.0
+    rows = []
+    for k, e in per.items():
+        ds = [v for v in e.values() if "MfmaUtil" in v and "MfmaFlopsBF16" in v]
+        if not ds:
+            continue
+        fl = sum(v["MfmaFlopsBF16"] for v in ds)
+        ns = sum(v["dur"] for v in ds)
+        util = sum(v["MfmaUtil"] for v in ds) / len(ds)
+        tot_fl += fl
+        tot_ns += ns
+        rows.append((ns, f"| `{k}` | {len(ds)} | {fl / len(ds):.4g} | {ns / len(ds) / 1e3:.2f} | "
+                         f"{fl / max(ns, 1) / 1e3:.1f} | {util:.2f} |"))
+    out += [r for _, r in sorted(rows, reverse=True)]
+    out.append(f"\nall listed kernels: {tot_fl / max(tot_ns, 1) / 1e3:.1f} TFLOP/s of BF16 matrix-core work "
+               f"over their summed durations")
+    return "\n".join(out)
+
+
 def main(argv):
+    if argv[0] == "mfma":
+        print(mfma(argv[1], argv[2:] or ["mconv_kernel", "mstep_kernel"]))
+        return
     if argv[0] == "replay":
         print(replay_run(argv[1], argv[2]))
         return
