@@ -188,3 +188,44 @@ def test_fullsize_batched_64_problems_bitwise_and_true_residuals():
         worst = max(worst, err)
         assert err <= 1e-10, (p["n"], ib["relres_true"], true)
     say(f"  {len(probs)} problems bitwise equal; worst true-residual mismatch {worst:.2e}")
+
+
+def test_fullsize_born_green_and_born_mcmg():
+    """The Born-series form at the 1056^2 benchmark size (the 1024^2 medium
+    with a 16-cell sponge layer, periodic operator): the background
+    (k0^2, eps) and the discrete Green operator G against the oracle's FFT,
+    and three Born+McMg steps (FP32 V-cycle) whose residual history and
+    iterate follow the oracle's."""
+    from oracle import born
+    from paper_2606_30495_amd import Handle
+    say("[full-born] grf1024 + sponge")
+    w = _workload("grf1024")
+    cfg = w["cfg"]
+    c, omega, h = w["c"], w["omega"], w["h"]
+    gm = helmholtz.default_gamma_max(omega, c, cfg.npml, h)
+    op = born.sponge_operator(c, omega, h, cfg.npml, gamma_max=gm)
+    bg = born.background(op)
+    H = Handle(c, omega, h, cfg.npml, w["blob"], precision="fp32", restart=2,
+               sigma_max=gm, absorber="sponge")
+    H.born_setup()
+    k0sq, eps = H.born_params()
+    assert abs(k0sq - bg["k0sq"]) <= 1e-12 * bg["k0sq"]
+    assert abs(eps - bg["eps"]) <= 1e-12 * bg["eps"]
+    x = synth.random_rhs(H.ext_shape, 31)
+    y = to_dev(np.zeros_like(x))
+    H.born_green(to_dev(x), y)
+    eg = rel_l2(to_host(y), born.green(bg, x))
+    say(f"  G relL2 = {eg:.3e}")
+    assert eg <= 1e-12, eg
+    f = w["f"]
+    u = to_dev(np.zeros_like(f))
+    info = H.born_solve(to_dev(f), u, method="mcmg", tol=1e-6, maxit=3)
+    ug = to_host(u)
+    H.close()
+    uo, io = born.born_mcmg(op, bg, _preconditioner(w), f, tol=1e-6, maxit=3)
+    hg, ho = np.array(info["hist"]), np.array(io["hist"])
+    e_u = rel_l2(ug, uo)
+    say(f"  hist gpu {hg} oracle {ho}; iterate relL2 {e_u:.2e}")
+    assert info["iters"] == io["iters"] == 3
+    assert np.max(np.abs(hg - ho) / ho) < 1e-4
+    assert e_u < 1e-4
