@@ -342,7 +342,8 @@ hipError_t Engine::body(bool all_phases) {
       ECK(kb_launch(KB_MULTIDOT, kb, pass, m_, s_));
       ECK(kb_launch(KB_REDUCE_DOTS, kb, pass, m_, s_));
       ECK(kb_launch(KB_UPDATE, kb, pass, m_, s_));
-      ECK(kb_launch(KB_REDUCE_NORM, kb, pass, m_, s_));
+      // the second pass's norm reduce runs inside the Givens launch
+      if (pass == 0) ECK(kb_launch(KB_REDUCE_NORM, kb, pass, m_, s_));
     }
     ECK(kb_launch(KB_GIVENS, kb, 0, m_, s_));
     ECK(kb_launch(KB_SCALE_W, kb, 0, m_, s_));

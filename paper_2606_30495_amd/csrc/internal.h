@@ -201,11 +201,13 @@ hipError_t launch_reduce_norm(const double* partial, int nb, const double* wnorm
                               hipStream_t s);
 hipError_t launch_scale(const double* w, const double* hn, double* v, long long n,
                         hipStream_t s);
-// Givens rotation step on column j of H (complex, column-major, ldh rows).
-// State: cs[m], sn[m] (complex), g[m+1] (complex).  Writes out[0] = |g_{j+1}|,
-// out[1] = hn, out[2] = column norm before rotation.
-hipError_t launch_givens(double* H, int ldh, int j, const double* hn, double* cs,
-                         double* sn, double* g, double* out, hipStream_t s);
+// launch_reduce_norm for pass 1 (skipped when skip[0] != 0), then the Givens
+// rotation step on column j of H (complex, column-major, ldh rows), in one
+// launch.  State: cs[m], sn[m] (complex), g[m+1] (complex).  Writes
+// out[0] = |g_{j+1}|, out[1] = hn, out[2] = column norm before rotation.
+hipError_t launch_norm_givens(const double* partial, int nb, const double* wnorm2, double* hn,
+                              int* skip, double* H, int ldh, int j, double* cs, double* sn,
+                              double* g, double* out, hipStream_t s);
 hipError_t launch_init_g(double* g, int m1, const double* beta, hipStream_t s);
 // y = H[0:k,0:k]^{-1} g[0:k] (upper triangular, complex).
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y,

@@ -229,27 +229,36 @@ __device__ __forceinline__ void reduce_norm_body(const double* __restrict__ part
   }
 }
 
-// Givens step on column j of H (complex, column-major, ldh rows).
-__device__ __forceinline__ void givens_body(double* H, int ldh, int j, const double* hn, double* cs,
-                                            double* sn, double* g, double* out) {
-  double* col = H + 2LL * j * ldh;
+// Givens step on column j of H (complex, column-major, ldh rows).  The
+// buffers are distinct, and the entry that the previous rotation produced is
+// carried in registers, so the loads of the column and of the rotations do
+// not wait on the stores of earlier rotations (one thread runs the chain).
+__device__ __forceinline__ void givens_body(double* __restrict__ H, int ldh, int j,
+                                            const double* __restrict__ hn,
+                                            double* __restrict__ cs, double* __restrict__ sn,
+                                            double* __restrict__ g, double* __restrict__ out) {
+  double* __restrict__ col = H + 2LL * j * ldh;
   const double b = hn[0];
-  col[2 * (j + 1)] = b;
-  col[2 * (j + 1) + 1] = 0.0;
+  // |column j| before rotation, h_{j+1,j} = b (real) in its last entry
   double cn = 0.0;
-  for (int i = 0; i <= j + 1; ++i) cn += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
+  for (int i = 0; i <= j; ++i) cn += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
+  cn += b * b;
   cn = sqrt(cn);
+  // x: entry i after rotations 0..i-1
+  double xr = col[0], xi = col[1];
+#pragma unroll 4
   for (int i = 0; i < j; ++i) {
-    const double xr = col[2 * i], xi = col[2 * i + 1];
     const double yr = col[2 * (i + 1)], yi = col[2 * (i + 1) + 1];
     const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
     // x' = c x + conj(s) y ; y' = -s x + c y
     col[2 * i] = c * xr + (sr * yr + si * yi);
     col[2 * i + 1] = c * xi + (sr * yi - si * yr);
-    col[2 * (i + 1)] = -(sr * xr - si * xi) + c * yr;
-    col[2 * (i + 1) + 1] = -(sr * xi + si * xr) + c * yi;
+    const double nr = -(sr * xr - si * xi) + c * yr;
+    const double ni = -(sr * xi + si * xr) + c * yi;
+    xr = nr;
+    xi = ni;
   }
-  const double ar = col[2 * j], ai = col[2 * j + 1];
+  const double ar = xr, ai = xi;
   const double aa = hypot(ar, ai);
   const double t = hypot(aa, b);
   double c, sr, si;
@@ -261,26 +270,31 @@ __device__ __forceinline__ void givens_body(double* H, int ldh, int j, const dou
     si = (-ai / aa) * (b / t);
   }
   cs[j] = c; sn[2 * j] = sr; sn[2 * j + 1] = si;
-  // new diagonal = c a + conj(s) b
+  // new diagonal = c a + conj(s) b; the rotation zeroes h_{j+1,j}
   col[2 * j] = c * ar + sr * b;
   col[2 * j + 1] = c * ai - si * b;
   col[2 * (j + 1)] = 0.0;
   col[2 * (j + 1) + 1] = 0.0;
   const double gr = g[2 * j], gi = g[2 * j + 1];
   // g_{j+1} = -s g_j ; g_j = c g_j
-  g[2 * (j + 1)] = -(sr * gr - si * gi);
-  g[2 * (j + 1) + 1] = -(sr * gi + si * gr);
+  const double g1r = -(sr * gr - si * gi), g1i = -(sr * gi + si * gr);
+  g[2 * (j + 1)] = g1r;
+  g[2 * (j + 1) + 1] = g1i;
   g[2 * j] = c * gr;
   g[2 * j + 1] = c * gi;
-  out[0] = hypot(g[2 * (j + 1)], g[2 * (j + 1) + 1]);
+  out[0] = hypot(g1r, g1i);
   out[1] = b;
   out[2] = cn;
 }
 
-__device__ __forceinline__ void backsolve_body(const double* H, int ldh, int k, const double* g,
-                                               double* y) {
+// Back substitution by one thread; H, g and y are distinct buffers, so the
+// loads of a row are independent of the stores of earlier rows.
+__device__ __forceinline__ void backsolve_body(const double* __restrict__ H, int ldh, int k,
+                                               const double* __restrict__ g,
+                                               double* __restrict__ y) {
   for (int i = k - 1; i >= 0; --i) {
     double sr = g[2 * i], si = g[2 * i + 1];
+#pragma unroll 4
     for (int l = i + 1; l < k; ++l) {
       const double hr = H[2 * ((long long)l * ldh + i)], hi = H[2 * ((long long)l * ldh + i) + 1];
       sr -= hr * y[2 * l] - hi * y[2 * l + 1];
@@ -374,10 +388,15 @@ __global__ void init_g_kernel(double* g, int m1, const double* beta) {
   }
 }
 
-__global__ void givens_kernel(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
-                              double* g, double* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  givens_body(H, ldh, j, hn, cs, sn, g, out);
+// The norm reduce of the second Gram-Schmidt pass (unless the device skipped
+// that pass) and the Givens step on column j, in one launch.
+__global__ __launch_bounds__(RB) void norm_givens_kernel(const double* __restrict__ partial, int nb,
+                                                         const double* wnorm2, double* hn,
+                                                         int* skip, double* H, int ldh, int j,
+                                                         double* cs, double* sn, double* g,
+                                                         double* out) {
+  if (!skip[0]) reduce_norm_body(partial, nb, wnorm2, hn, skip, 1, 0);
+  if (threadIdx.x == 0) givens_body(H, ldh, j, hn, cs, sn, g, out);
 }
 
 __global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
@@ -467,11 +486,17 @@ __global__ __launch_bounds__(RB) void kb_reduce_norm(const KArgs* __restrict__ t
                    pass == 0 ? A.always_two : 0);
 }
 
-__global__ void kb_givens(const KArgs* __restrict__ tab, const int* __restrict__ frozen,
-                          const int* __restrict__ jpos, double* __restrict__ gather) {
+// The second pass's norm reduce (unless skipped) and the Givens step.
+__global__ __launch_bounds__(RB) void kb_givens(const KArgs* __restrict__ tab,
+                                                const int* __restrict__ frozen,
+                                                const int* __restrict__ jpos,
+                                                double* __restrict__ gather) {
   const int p = blockIdx.x;
-  if (threadIdx.x != 0 || is_frozen(frozen, p)) return;
+  if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
+  if (!to_global<const int>(A.skip)[0])
+    reduce_norm_body(A.partial, red_blocks(A.N), A.scal + 8, A.scal + 9, A.skip, 1, 0);
+  if (threadIdx.x != 0) return;
   givens_body(A.H, A.ldh, jpos[p], A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
   gather[4 * p + 0] = A.scal[16];
   gather[4 * p + 1] = A.scal[17];
@@ -598,9 +623,11 @@ hipError_t launch_scale(const double* w, const double* hn, double* v, long long 
   return hipGetLastError();
 }
 
-hipError_t launch_givens(double* H, int ldh, int j, const double* hn, double* cs, double* sn,
-                         double* g, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(givens_kernel, dim3(1), dim3(64), 0, s, H, ldh, j, hn, cs, sn, g, out);
+hipError_t launch_norm_givens(const double* partial, int nb, const double* wnorm2, double* hn,
+                              int* skip, double* H, int ldh, int j, double* cs, double* sn,
+                              double* g, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(norm_givens_kernel, dim3(1), dim3(RB), 0, s, partial, nb, wnorm2, hn, skip, H,
+                     ldh, j, cs, sn, g, out);
   return hipGetLastError();
 }
 
@@ -662,7 +689,7 @@ hipError_t kb_launch(int op, const KBatch& b, int pass, int m, hipStream_t s) {
       hipLaunchKernelGGL(kb_reduce_norm, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, pass);
       break;
     case KB_GIVENS:
-      hipLaunchKernelGGL(kb_givens, dim3(b.np), dim3(64), 0, s, b.tab, b.frozen, b.jpos, b.gather);
+      hipLaunchKernelGGL(kb_givens, dim3(b.np), dim3(RB), 0, s, b.tab, b.frozen, b.jpos, b.gather);
       break;
     case KB_SCALE_R:
       hipLaunchKernelGGL(kb_scale, dim3(b.total_elem), dim3(RB), 0, s, b.tab, b.pre_elem, b.np,

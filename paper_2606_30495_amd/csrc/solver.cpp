@@ -134,8 +134,8 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       HCK(launch_reduce_dots(c->partial, nb, nv, c->coef, Hcol, c->scal + 10, c->skip, s));
       HCK(c->timed("update_kernel", 8.0 * N * (nv + 1), vb * (nv + 2),
                    [=] { return launch_update(c->V, N, nv, c->coef, c->wv, N, c->partial, c->skip, s); }));
-      HCK(launch_reduce_norm(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, 1, 0, s));
-      HCK(launch_givens(c->H, ldh, j, c->scal + 9, c->cs, c->sn, c->g, c->scal + 16, s));
+      HCK(launch_norm_givens(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, c->H, ldh, j,
+                             c->cs, c->sn, c->g, c->scal + 16, s));
       if (j + 1 < m) HCK(launch_scale(c->wv, c->scal + 9, c->V + 2LL * (j + 1) * N, N, s));
       HCK(read_scal(c, 16, 3));
       const double rho = c->host_scal[0], hn = c->host_scal[1], cn = c->host_scal[2];
