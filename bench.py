@@ -501,9 +501,9 @@ def progress(msg):
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(independent solves shard across GPUs without communication; see DESIGN.md)",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(independent solves shard across GPUs without communication, one process "
+              "per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
