@@ -229,81 +229,119 @@ __device__ __forceinline__ void reduce_norm_body(const double* __restrict__ part
   }
 }
 
-// Givens step on column j of H (complex, column-major, ldh rows).  The
-// buffers are distinct, and the entry that the previous rotation produced is
-// carried in registers, so the loads of the column and of the rotations do
-// not wait on the stores of earlier rotations (one thread runs the chain).
-__device__ __forceinline__ void givens_body(double* __restrict__ H, int ldh, int j,
-                                            const double* __restrict__ hn,
-                                            double* __restrict__ cs, double* __restrict__ sn,
-                                            double* __restrict__ g, double* __restrict__ out) {
+// Largest restart length (the handle rejects longer ones): bounds the LDS
+// copies of the Hessenberg columns below.
+constexpr int KMAX = 64;
+
+// Givens step on column j of H (complex, column-major, ldh rows), by one
+// block: the threads copy the column and the stored rotations to LDS, one
+// thread applies the rotations there in order (each on the entry the
+// previous one produced) and computes the new one, and the threads write
+// the column back.  hn[0] may have been written by thread 0 of this block.
+__device__ __forceinline__ void givens_block(double* __restrict__ H, int ldh, int j,
+                                             const double* hn, double* __restrict__ cs,
+                                             double* __restrict__ sn, double* __restrict__ g,
+                                             double* out) {
+  __shared__ double2 colS[KMAX + 1];
+  __shared__ double2 snS[KMAX];
+  __shared__ double csS[KMAX];
   double* __restrict__ col = H + 2LL * j * ldh;
-  const double b = hn[0];
-  // |column j| before rotation, h_{j+1,j} = b (real) in its last entry
-  double cn = 0.0;
-  for (int i = 0; i <= j; ++i) cn += col[2 * i] * col[2 * i] + col[2 * i + 1] * col[2 * i + 1];
-  cn += b * b;
-  cn = sqrt(cn);
-  // x: entry i after rotations 0..i-1
-  double xr = col[0], xi = col[1];
-#pragma unroll 4
-  for (int i = 0; i < j; ++i) {
-    const double yr = col[2 * (i + 1)], yi = col[2 * (i + 1) + 1];
-    const double c = cs[i], sr = sn[2 * i], si = sn[2 * i + 1];
-    // x' = c x + conj(s) y ; y' = -s x + c y
-    col[2 * i] = c * xr + (sr * yr + si * yi);
-    col[2 * i + 1] = c * xi + (sr * yi - si * yr);
-    const double nr = -(sr * xr - si * xi) + c * yr;
-    const double ni = -(sr * xi + si * xr) + c * yi;
-    xr = nr;
-    xi = ni;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int i = tid; i <= j; i += nt) colS[i] = make_double2(col[2 * i], col[2 * i + 1]);
+  for (int i = tid; i < j; i += nt) {
+    csS[i] = cs[i];
+    snS[i] = make_double2(sn[2 * i], sn[2 * i + 1]);
   }
-  const double ar = xr, ai = xi;
-  const double aa = hypot(ar, ai);
-  const double t = hypot(aa, b);
-  double c, sr, si;
-  if (aa == 0.0) { c = 0.0; sr = 1.0; si = 0.0; }
-  else {
-    c = aa / t;
-    // s = (conj(a) / |a|) * (b / t)
-    sr = (ar / aa) * (b / t);
-    si = (-ai / aa) * (b / t);
+  __syncthreads();
+  if (tid == 0) {
+    const double b = hn[0];
+    // |column j| before rotation, h_{j+1,j} = b (real) in its last entry
+    double cn = 0.0;
+    for (int i = 0; i <= j; ++i) cn += colS[i].x * colS[i].x + colS[i].y * colS[i].y;
+    cn += b * b;
+    cn = sqrt(cn);
+    // x: entry i after rotations 0..i-1
+    double xr = colS[0].x, xi = colS[0].y;
+    for (int i = 0; i < j; ++i) {
+      const double yr = colS[i + 1].x, yi = colS[i + 1].y;
+      const double c = csS[i], sr = snS[i].x, si = snS[i].y;
+      // x' = c x + conj(s) y ; y' = -s x + c y
+      colS[i] = make_double2(c * xr + (sr * yr + si * yi), c * xi + (sr * yi - si * yr));
+      const double nr = -(sr * xr - si * xi) + c * yr;
+      const double ni = -(sr * xi + si * xr) + c * yi;
+      xr = nr;
+      xi = ni;
+    }
+    const double ar = xr, ai = xi;
+    const double aa = hypot(ar, ai);
+    const double t = hypot(aa, b);
+    double c, sr, si;
+    if (aa == 0.0) { c = 0.0; sr = 1.0; si = 0.0; }
+    else {
+      c = aa / t;
+      // s = (conj(a) / |a|) * (b / t)
+      sr = (ar / aa) * (b / t);
+      si = (-ai / aa) * (b / t);
+    }
+    cs[j] = c; sn[2 * j] = sr; sn[2 * j + 1] = si;
+    // new diagonal = c a + conj(s) b; the rotation zeroes h_{j+1,j}
+    colS[j] = make_double2(c * ar + sr * b, c * ai - si * b);
+    colS[j + 1] = make_double2(0.0, 0.0);
+    const double gr = g[2 * j], gi = g[2 * j + 1];
+    // g_{j+1} = -s g_j ; g_j = c g_j
+    const double g1r = -(sr * gr - si * gi), g1i = -(sr * gi + si * gr);
+    g[2 * (j + 1)] = g1r;
+    g[2 * (j + 1) + 1] = g1i;
+    g[2 * j] = c * gr;
+    g[2 * j + 1] = c * gi;
+    out[0] = hypot(g1r, g1i);
+    out[1] = b;
+    out[2] = cn;
   }
-  cs[j] = c; sn[2 * j] = sr; sn[2 * j + 1] = si;
-  // new diagonal = c a + conj(s) b; the rotation zeroes h_{j+1,j}
-  col[2 * j] = c * ar + sr * b;
-  col[2 * j + 1] = c * ai - si * b;
-  col[2 * (j + 1)] = 0.0;
-  col[2 * (j + 1) + 1] = 0.0;
-  const double gr = g[2 * j], gi = g[2 * j + 1];
-  // g_{j+1} = -s g_j ; g_j = c g_j
-  const double g1r = -(sr * gr - si * gi), g1i = -(sr * gi + si * gr);
-  g[2 * (j + 1)] = g1r;
-  g[2 * (j + 1) + 1] = g1i;
-  g[2 * j] = c * gr;
-  g[2 * j + 1] = c * gi;
-  out[0] = hypot(g1r, g1i);
-  out[1] = b;
-  out[2] = cn;
+  __syncthreads();
+  for (int i = tid; i <= j + 1; i += nt) {
+    col[2 * i] = colS[i].x;
+    col[2 * i + 1] = colS[i].y;
+  }
 }
 
-// Back substitution by one thread; H, g and y are distinct buffers, so the
-// loads of a row are independent of the stores of earlier rows.
-__device__ __forceinline__ void backsolve_body(const double* __restrict__ H, int ldh, int k,
-                                               const double* __restrict__ g,
-                                               double* __restrict__ y) {
-  for (int i = k - 1; i >= 0; --i) {
-    double sr = g[2 * i], si = g[2 * i + 1];
-#pragma unroll 4
-    for (int l = i + 1; l < k; ++l) {
-      const double hr = H[2 * ((long long)l * ldh + i)], hi = H[2 * ((long long)l * ldh + i) + 1];
-      sr -= hr * y[2 * l] - hi * y[2 * l + 1];
-      si -= hr * y[2 * l + 1] + hi * y[2 * l];
+// y = H[0:k,0:k]^{-1} g[0:k] by back substitution, by one block: the
+// threads copy the upper triangle of H (packed by columns) and g to LDS, one
+// thread substitutes there (row k-1 first, each row's sum in column order),
+// and the threads write y.
+__device__ __forceinline__ void backsolve_block(const double* __restrict__ H, int ldh, int k,
+                                                const double* __restrict__ g,
+                                                double* __restrict__ y) {
+  __shared__ double2 tri[KMAX * (KMAX + 1) / 2];
+  __shared__ double2 ys[KMAX];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int l = 0; l < k; ++l) {
+    const long long c = (long long)l * ldh;
+    const int o = l * (l + 1) / 2;
+    for (int i = tid; i <= l; i += nt) tri[o + i] = make_double2(H[2 * (c + i)], H[2 * (c + i) + 1]);
+  }
+  for (int i = tid; i < k; i += nt) ys[i] = make_double2(g[2 * i], g[2 * i + 1]);
+  __syncthreads();
+  if (tid == 0) {
+    for (int i = k - 1; i >= 0; --i) {
+      double sr = ys[i].x, si = ys[i].y;
+      for (int l = i + 1; l < k; ++l) {
+        const double2 h = tri[l * (l + 1) / 2 + i];
+        const double hr = h.x, hi = h.y;
+        const double yr = ys[l].x, yi = ys[l].y;
+        sr -= hr * yr - hi * yi;
+        si -= hr * yi + hi * yr;
+      }
+      const double2 d = tri[i * (i + 1) / 2 + i];
+      const double dr = d.x, di = d.y;
+      const double q = dr * dr + di * di;
+      ys[i] = make_double2((sr * dr + si * di) / q, (si * dr - sr * di) / q);
     }
-    const double dr = H[2 * ((long long)i * ldh + i)], di = H[2 * ((long long)i * ldh + i) + 1];
-    const double q = dr * dr + di * di;
-    y[2 * i] = (sr * dr + si * di) / q;
-    y[2 * i + 1] = (si * dr - sr * di) / q;
+  }
+  __syncthreads();
+  for (int i = tid; i < k; i += nt) {
+    y[2 * i] = ys[i].x;
+    y[2 * i + 1] = ys[i].y;
   }
 }
 
@@ -396,12 +434,12 @@ __global__ __launch_bounds__(RB) void norm_givens_kernel(const double* __restric
                                                          double* cs, double* sn, double* g,
                                                          double* out) {
   if (!skip[0]) reduce_norm_body(partial, nb, wnorm2, hn, skip, 1, 0);
-  if (threadIdx.x == 0) givens_body(H, ldh, j, hn, cs, sn, g, out);
+  givens_block(H, ldh, j, hn, cs, sn, g, out);
 }
 
-__global__ void backsolve_kernel(const double* H, int ldh, int k, const double* g, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  backsolve_body(H, ldh, k, g, y);
+__global__ __launch_bounds__(64) void backsolve_kernel(const double* H, int ldh, int k,
+                                                       const double* g, double* y) {
+  backsolve_block(H, ldh, k, g, y);
 }
 
 __global__ __launch_bounds__(RB) void zupdate_kernel(const float* __restrict__ Z, long long ldz,
@@ -496,8 +534,8 @@ __global__ __launch_bounds__(RB) void kb_givens(const KArgs* __restrict__ tab,
   const KArgs& A = tab[p];
   if (!to_global<const int>(A.skip)[0])
     reduce_norm_body(A.partial, red_blocks(A.N), A.scal + 8, A.scal + 9, A.skip, 1, 0);
+  givens_block(A.H, A.ldh, jpos[p], A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
   if (threadIdx.x != 0) return;
-  givens_body(A.H, A.ldh, jpos[p], A.scal + 9, A.cs, A.sn, A.g, A.scal + 16);
   gather[4 * p + 0] = A.scal[16];
   gather[4 * p + 1] = A.scal[17];
   gather[4 * p + 2] = A.scal[18];
@@ -531,12 +569,13 @@ __global__ __launch_bounds__(RB) void kb_cycle_init(const KArgs* __restrict__ ta
   for (int i = threadIdx.x; i < 2 * (m + 1); i += RB) A.g[i] = (i == 0) ? A.scal[3] : 0.0;
 }
 
-__global__ void kb_backsolve(const KArgs* __restrict__ tab, const int* __restrict__ frozen,
-                             const int* __restrict__ kk) {
+__global__ __launch_bounds__(64) void kb_backsolve(const KArgs* __restrict__ tab,
+                                                   const int* __restrict__ frozen,
+                                                   const int* __restrict__ kk) {
   const int p = blockIdx.x;
-  if (threadIdx.x != 0 || is_frozen(frozen, p)) return;
+  if (is_frozen(frozen, p)) return;
   const KArgs& A = tab[p];
-  if (kk[p] > 0) backsolve_body(A.H, A.ldh, kk[p], A.g, A.y);
+  if (kk[p] > 0) backsolve_block(A.H, A.ldh, kk[p], A.g, A.y);
 }
 
 __global__ __launch_bounds__(RB) void kb_zupdate(const KArgs* __restrict__ tab,
@@ -626,6 +665,7 @@ hipError_t launch_scale(const double* w, const double* hn, double* v, long long 
 hipError_t launch_norm_givens(const double* partial, int nb, const double* wnorm2, double* hn,
                               int* skip, double* H, int ldh, int j, double* cs, double* sn,
                               double* g, double* out, hipStream_t s) {
+  if (j < 0 || j >= KMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(norm_givens_kernel, dim3(1), dim3(RB), 0, s, partial, nb, wnorm2, hn, skip, H,
                      ldh, j, cs, sn, g, out);
   return hipGetLastError();
@@ -638,6 +678,7 @@ hipError_t launch_init_g(double* g, int m1, const double* beta, hipStream_t s) {
 
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y,
                             hipStream_t s) {
+  if (k < 0 || k > KMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
   return hipGetLastError();
 }
@@ -672,6 +713,7 @@ hipError_t launch_copy_f64(const double* a, double* b, long long n, hipStream_t 
 
 hipError_t kb_launch(int op, const KBatch& b, int pass, int m, hipStream_t s) {
   if (b.np == 0) return hipSuccess;
+  if (m < 1 || m > KMAX) return hipErrorInvalidValue;   // LDS copies of H columns
   switch (op) {
     case KB_MULTIDOT:
       hipLaunchKernelGGL(kb_multidot, dim3(b.total_red), dim3(RB), 0, s, b.tab, b.pre_red, b.np,

@@ -13,13 +13,13 @@ from test_gpu_solve import classical_problem, gpu_handle
 pytestmark = pytest.mark.gpu
 
 
-def _problems(precision):
+def _problems(precision, ortho=0):
     sides = [(48, 6), (64, 8), (40, 4)]
     probs, handles = [], []
     for n, npml in sides:
         p = classical_problem(n=n, npml=npml)
         probs.append(p)
-        handles.append(gpu_handle(p, precision))
+        handles.append(gpu_handle(p, precision, ortho=ortho))
     # a second right-hand side for the 64^2 medium (same handle twice)
     rng = np.random.default_rng(9)
     f2 = synth.point_source(64, 8, tuple(rng.uniform(0.2, 0.8, 2)), 2)
@@ -28,11 +28,13 @@ def _problems(precision):
     return handles, items
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
-def test_batch_matches_single_solves(precision):
+@pytest.mark.parametrize("precision,ortho", [("fp32", 0), ("bf16", 0), ("fp32", 1)])
+def test_batch_matches_single_solves(precision, ortho):
+    """ortho = 1 forces the second Gram-Schmidt pass on every column, so the
+    pass's norm reduce inside the Givens launch runs for every problem."""
     from paper_2606_30495_amd import solve_batch
-    say(f"[batch] {precision}")
-    handles, items = _problems(precision)
+    say(f"[batch] {precision} ortho {ortho}")
+    handles, items = _problems(precision, ortho)
     singles = []
     for H, f in items:
         u = to_dev(np.zeros_like(f))

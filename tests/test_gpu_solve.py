@@ -25,10 +25,10 @@ def classical_problem(n=64, npml=8, channels=(2, 8, 16), ppw=10.0, src=(0.5, 0.2
             "blob": synth.pack_blob(2, channels, nu, nu, tens)}
 
 
-def gpu_handle(p, precision="fp32", restart=30):
+def gpu_handle(p, precision="fp32", restart=30, ortho=0):
     from paper_2606_30495_amd import Handle
     H = Handle(p["c"], p["omega"], p["h"], p["npml"], p["blob"], precision=precision, restart=restart,
-               absorber=p.get("absorber", "pml"))
+               absorber=p.get("absorber", "pml"), ortho=ortho)
     for l, (a, s) in enumerate(p["feats"], start=1):
         H.set_features(l, to_dev(a), to_dev(s))
     return H
@@ -83,6 +83,29 @@ def test_classical_history_tracks_oracle():
     info = H.solve(to_dev(p["f"]), u, tol=1e-6, maxit=500)
     hg, ho = np.array(info["hist"][:60]), np.array(io["hist"][:60])
     assert np.max(np.abs(hg - ho) / ho) < 1e-4
+
+
+def test_always_two_pass_orthogonalisation_tracks_oracle():
+    """Classical Gram-Schmidt with the second pass forced on every column
+    (ortho = 1) against the gated default and the oracle's modified
+    Gram-Schmidt: both follow the oracle's residual estimates to 1e-4
+    relative over the first 60 iterations (two restart cycles), and both
+    converge in the oracle's iteration count +/- 1."""
+    say("[ortho-two-pass]")
+    p = classical_problem()
+    uo, io = _oracle_cached("bump64", p)
+    ho = np.array(io["hist"][:60])
+    for ortho in (1, 0):
+        H = gpu_handle(p, ortho=ortho)
+        u = to_dev(np.zeros_like(p["f"]))
+        info = H.solve(to_dev(p["f"]), u, tol=1e-6, maxit=500)
+        H.close()
+        hg = np.array(info["hist"][:60])
+        err = np.max(np.abs(hg - ho) / ho)
+        say(f"  ortho {ortho}: iters {info['iters']} (oracle {io['iters']}), hist err {err:.2e}")
+        assert info["converged"] and info["relres_true"] <= 1e-6
+        assert abs(info["iters"] - io["iters"]) <= 1
+        assert err < 1e-4
 
 
 def test_warm_restart_and_maxit():
