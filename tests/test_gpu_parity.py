@@ -216,6 +216,29 @@ def test_fgmres_history_matches_oracle():
     assert rel_l2(to_host(u), uo) < 1e-3
 
 
+def test_fgmres_longest_restart_history_matches_oracle():
+    """Restart length 64, the longest the library takes (random-init weights,
+    bump64): 66 iterations run a whole cycle, whose last Givens step works on
+    column 63 and whose back substitution solves a 64 x 64 system, then two
+    iterations of the next cycle.  The residual history and the iterate
+    follow the oracle's FGMRES(64)."""
+    say("[fgmres-m64]")
+    p = problem(2, 64, 8, (2, 8, 16))
+    op, W, M = oracle_parts(p)
+    H = handle(p, restart=64)
+    f = synth.point_source(64, 8, (0.5, 0.25), 2)
+    u = to_dev(np.zeros_like(f))
+    info = H.solve(to_dev(f), u, tol=1e-6, maxit=66)
+    uo, io = krylov.fgmres(lambda x: helmholtz.apply(op, x), M, f, m=64, tol=1e-6, maxit=66)
+    say(f"  gpu iters {info['iters']} rel {info['relres_true']:.6e}; oracle {io['iters']} {io['relres_true']:.6e}")
+    assert info["iters"] == io["iters"] == 66
+    hg, ho = np.array(info["hist"]), np.array(io["hist"])
+    assert len(hg) == len(ho)
+    assert np.max(np.abs(hg - ho) / ho) < 1e-5
+    assert abs(info["relres_true"] - io["relres_true"]) / io["relres_true"] < 1e-5
+    assert rel_l2(to_host(u), uo) < 1e-3
+
+
 def test_fgmres_small_pml_vs_oracle():
     """16x16 + 4-cell PML with restart 64: GPU and oracle iterates agree
     after 128 iterations."""
