@@ -27,8 +27,8 @@ Parity pins (tests/test_oracle_mcmg.py): linearity in r for real scalars and
 MG(0) = 0 (Sec. 3.2), exact locality against the receptive field, adjointness
 of R and P when P carries R's tensor, reduction to a textbook geometric
 multigrid V-cycle with hand-set weights (Sec. 2.2, App. A.3 smoother), and
-closed-form setup features for one-hot kernels.  Setup values for random
-weights are otherwise parity unpinned (no printed values in the paper).
+closed-form setup features for one-hot kernels in each step of Alg. 1 (the
+paper prints no feature values to compare against).
 """
 import numpy as np
 
