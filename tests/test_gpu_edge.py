@@ -1,0 +1,98 @@
+"""Degenerate inputs through the C ABI: a zero right-hand side, maxit = 0,
+an initial guess that already solves the system, a non-finite right-hand
+side, and the V-cycle on a single-node impulse at a corner of the extended
+grid (every level's zero padding on two sides at once)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+import synth
+from _gpu_common import handle, oracle_parts, problem, rel_l2, say, to_dev, to_host
+from oracle import helmholtz
+
+pytestmark = pytest.mark.gpu
+
+
+def _small():
+    p = problem(2, 32, 6, (2, 8, 16))
+    op, W, M = oracle_parts(p)
+    f = synth.point_source(32, 6, (0.5, 0.25), 2)
+    return p, op, M, f
+
+
+@pytest.mark.parametrize("method", ["solve", "stationary"])
+def test_zero_rhs_gives_zero_at_once(method):
+    """f = 0: status OK after zero iterations and u = 0, whatever u held."""
+    say(f"[edge-zero-rhs] {method}")
+    p, op, M, f = _small()
+    H = handle(p)
+    u = to_dev(synth.random_rhs(f.shape, 5))
+    info = getattr(H, method)(to_dev(np.zeros_like(f)), u, tol=1e-6, maxit=50)
+    H.close()
+    assert info["status"] == 0 and info["converged"] and info["iters"] == 0
+    assert np.all(to_host(u) == 0)
+
+
+@pytest.mark.parametrize("method", ["solve", "stationary"])
+def test_maxit_zero_reports_the_initial_residual(method):
+    """maxit = 0: NOT_CONVERGED, no iteration, u untouched, and the reported
+    true residual is the oracle's |f - A u0| / |f| for the initial guess."""
+    say(f"[edge-maxit0] {method}")
+    p, op, M, f = _small()
+    H = handle(p)
+    u0 = 1e-3 * synth.random_rhs(f.shape, 6)
+    u = to_dev(u0)
+    info = getattr(H, method)(to_dev(f), u, tol=1e-6, maxit=0)
+    H.close()
+    assert info["status"] == 1 and not info["converged"] and info["iters"] == 0
+    assert np.array_equal(to_host(u), u0)
+    true = np.linalg.norm(f - helmholtz.apply(op, u0)) / np.linalg.norm(f)
+    assert abs(info["relres_true"] - true) <= 1e-12 * true
+
+
+def test_exact_initial_guess_needs_no_iteration():
+    """u0 = the sparse direct solution: converged after zero iterations with
+    u unchanged."""
+    say("[edge-exact-u0]")
+    p, op, M, f = _small()
+    A = helmholtz.assemble(op).tocsc()
+    u0 = spla.spsolve(A, f.ravel()).reshape(f.shape)
+    H = handle(p)
+    u = to_dev(u0)
+    info = H.solve(to_dev(f), u, tol=1e-6, maxit=50)
+    H.close()
+    say(f"  relres_true {info['relres_true']:.3e}")
+    assert info["converged"] and info["iters"] == 0
+    assert info["relres_true"] < 1e-10
+    assert np.array_equal(to_host(u), u0)
+
+
+def test_nonfinite_rhs_is_an_error():
+    from paper_2606_30495_amd._lib import McmgError
+    say("[edge-nan]")
+    p, op, M, f = _small()
+    bad = f.copy()
+    bad[10, 10] = np.nan
+    H = handle(p)
+    u = to_dev(np.zeros_like(f))
+    with pytest.raises(McmgError) as exc:
+        H.solve(to_dev(bad), u, tol=1e-6, maxit=10)
+    H.close()
+    assert exc.value.status == -5          # MCMG_E_NONFINITE
+
+
+@pytest.mark.parametrize("corner", [(0, 0), (-1, -1), (0, -1)])
+def test_vcycle_corner_impulse_matches_oracle(corner):
+    """A unit impulse (real and imaginary parts) on a corner node of the
+    extended grid, FP32 V-cycle, against the FP64 oracle to 1e-5."""
+    say(f"[edge-corner] {corner}")
+    p, op, M, f = _small()
+    r = np.zeros_like(f)
+    r[corner] = 1.0 - 0.5j
+    H = handle(p)
+    z = to_dev(np.zeros_like(r))
+    H.apply(to_dev(r), z)
+    H.close()
+    err = rel_l2(to_host(z), M(r))
+    say(f"  relL2 {err:.3e}")
+    assert err <= 1e-5, err
