@@ -52,6 +52,40 @@ def test_batch_matches_single_solves(precision, ortho):
         assert np.array_equal(np.array(i2["hist"]), np.array(i1["hist"]))
 
 
+def test_batch_zero_rhs_and_solved_guess_in_a_mix():
+    """One batch holding a zero right-hand side (u set to zero at once, from
+    a nonzero guess), a right-hand side whose initial guess is the sparse
+    direct solution (no iteration, u untouched) and two ordinary problems:
+    each result is bitwise equal to its single solve."""
+    import scipy.sparse.linalg as spla
+    from oracle import helmholtz
+    from paper_2606_30495_amd import solve_batch
+    say("[batch-edge]")
+    handles, items = _problems("fp32")
+    fs = [f for _, f in items]
+    fs[0] = np.zeros_like(fs[0])
+    p2 = classical_problem(n=40, npml=4)
+    op2 = helmholtz.setup_operator(p2["c"], p2["omega"], p2["h"], p2["npml"])
+    exact = spla.spsolve(helmholtz.assemble(op2).tocsc(), fs[2].ravel()).reshape(fs[2].shape)
+    u0s = [synth.random_rhs(fs[0].shape, 8), np.zeros_like(fs[1]), exact, np.zeros_like(fs[3])]
+    singles = []
+    for (H, _), f, u0 in zip(items, fs, u0s):
+        u = to_dev(u0)
+        info = H.solve(to_dev(f), u, tol=1e-6, maxit=500)
+        singles.append((to_host(u), info))
+    us = [to_dev(u0) for u0 in u0s]
+    st, infos = solve_batch([H for H, _ in items], [to_dev(f) for f in fs], us, tol=1e-6,
+                            maxit=500, hist_cap=600)
+    assert st == 0
+    for k, ((u1, i1), ub, i2) in enumerate(zip(singles, us, infos)):
+        say(f"  problem {k}: single {i1['iters']} it, batch {i2['iters']} it")
+        assert i2["converged"] and i2["iters"] == i1["iters"]
+        assert np.array_equal(to_host(ub), u1)
+    assert infos[0]["iters"] == 0 and np.all(to_host(us[0]) == 0)
+    assert infos[2]["iters"] == 0 and np.array_equal(to_host(us[2]), exact)
+    assert infos[1]["iters"] > 0 and infos[3]["iters"] > 0
+
+
 def test_batch_alone_equals_in_mix():
     """The same problem alone in a batch of one and inside a larger batch."""
     from paper_2606_30495_amd import solve_batch
