@@ -103,3 +103,30 @@ def test_vcycle_corner_impulse_matches_oracle(corner, precision, tol):
     err = rel_l2(to_host(z), M(r))
     say(f"  relL2 {err:.3e}")
     assert err <= tol, err
+
+
+@pytest.mark.parametrize("method", ["mcmg", "cbs"])
+def test_born_zero_rhs_and_maxit_zero(method):
+    """The Born-series iteration: f = 0 returns u = 0 after no step; with
+    maxit = 0 it reports the oracle's periodic residual |f - A_per u0| / |f|
+    of the initial guess and leaves u untouched."""
+    from oracle import born
+    from paper_2606_30495_amd import Handle
+    say(f"[edge-born] {method}")
+    p = problem(2, 32, 6, (2, 8, 16))
+    gm = helmholtz.default_gamma_max(p["omega"], p["c"], p["npml"], p["h"])
+    H = Handle(p["c"], p["omega"], p["h"], p["npml"], p["blob"], precision="fp32", restart=4,
+               sigma_max=gm, absorber="sponge")
+    op = born.sponge_operator(p["c"], p["omega"], p["h"], p["npml"], gamma_max=gm)
+    f = synth.point_source(32, 6, (0.5, 0.25), 2)
+    u = to_dev(synth.random_rhs(f.shape, 9))
+    info = H.born_solve(to_dev(np.zeros_like(f)), u, method=method, tol=1e-6, maxit=20)
+    assert info["status"] == 0 and info["iters"] == 0 and np.all(to_host(u) == 0)
+    u0 = 1e-3 * synth.random_rhs(f.shape, 10)
+    u = to_dev(u0)
+    info = H.born_solve(to_dev(f), u, method=method, tol=1e-6, maxit=0)
+    H.close()
+    assert info["status"] == 1 and info["iters"] == 0
+    assert np.array_equal(to_host(u), u0)
+    true = np.linalg.norm(f - born.apply_periodic(op, u0)) / np.linalg.norm(f)
+    assert abs(info["relres_true"] - true) <= 1e-12 * true
