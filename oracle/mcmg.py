@@ -26,8 +26,10 @@ Readings where the paper is silent:
 Parity pins (tests/test_oracle_mcmg.py): linearity in r for real scalars and
 MG(0) = 0 (Sec. 3.2), exact locality against the receptive field, adjointness
 of R and P when P carries R's tensor, reduction to a textbook geometric
-multigrid V-cycle with hand-set weights (Sec. 2.2, App. A.3 smoother), and
-closed-form setup features for one-hot kernels in each step of Alg. 1 (the
+multigrid V-cycle with hand-set weights (Sec. 2.2, App. A.3 smoother), the
+order of feature modulation of Eq. pyhs_conv (the feature multiplies the
+convolution's output, in A_l and in S_l) by a closed form with spatially
+varying features and one-hot off-centre kernels, and closed-form setup features for one-hot kernels in each step of Alg. 1 (the
 paper prints no feature values to compare against).
 """
 import numpy as np

@@ -243,3 +243,109 @@ def test_setup_one_hot_closed_form():
     assert F["a"][2].shape == (2, nc, nc)
     assert np.allclose(F["a"][2][1], expect, atol=1e-15, rtol=1e-14)
     assert np.allclose(F["a"][2][0], 0.0)
+
+
+def _tap_index(off):
+    """Row-major tap index of an offset in {-1, 0, 1}^D."""
+    idx = 0
+    for o in off:
+        idx = 3 * idx + (o + 1)
+    return idx
+
+
+def _modulation_case(dim):
+    """One level, nu1 = 2, spatially varying features, one-hot off-centre
+    kernels on distinct channel pairs, identity lift/projection."""
+    n = 11
+    channels = (2,)
+    tens = synth.make_weights(dim, channels, (2,), (0,), 0)
+    for t in tens:
+        t["w"] = np.zeros_like(t["w"])
+    get = {(t["kind"], t["step"]): t for t in tens}
+    ctr = _tap_index((0,) * dim)
+    for kind in ("g_lift", "g_proj"):
+        get[(kind, 0)]["w"][0, 0, ctr] = get[(kind, 0)]["w"][1, 1, ctr] = 1.0
+    # offsets (the input a one-hot tap reads, relative to the output node)
+    sS = (1, 0) if dim == 2 else (1, 0, -1)
+    sA = (-1, -1) if dim == 2 else (-1, -1, 0)
+    sW = (0, 1) if dim == 2 else (0, 1, 1)
+    s1 = (0, -1) if dim == 2 else (0, -1, 1)
+    s2 = (1, 1) if dim == 2 else (1, 1, -1)
+    wW = 0.75
+    get[("KS", 0)]["w"][1, 0, _tap_index(sS)] = 1.0    # channel 0 -> 1
+    get[("KA", 0)]["w"][0, 1, _tap_index(sA)] = 1.0    # channel 1 -> 0
+    get[("W", 0)]["w"][0, 1, _tap_index(sW)] = wW      # channel 1 -> 0
+    get[("Wsm", 1)]["w"][1, 1, _tap_index(s1)] = 1.0
+    get[("Wsm", 2)]["w"][1, 1, _tap_index(s2)] = 1.0
+    W = mcmg.Weights(dim, channels, (2,), (0,), tens)
+    rng = np.random.default_rng(11)
+    shape = (n,) * dim
+    a = rng.uniform(0.5, 2.0, size=(2,) + shape)
+    s = rng.uniform(0.5, 2.0, size=(2,) + shape)
+    feats = {"a": [None, a], "s": [None, s]}
+    x0 = (5,) * dim
+    return W, feats, shape, x0, dict(sS=sS, sA=sA, sW=sW, s1=s1, s2=s2, wW=wW)
+
+
+def _modulation_expected(feats, shape, x0, o):
+    """Closed form of Alg. 2 for the case above on an impulse r = delta_{x0}
+    (real part), with Eq. pyhs_conv's order c (.) (K_x * x): a one-hot tap
+    reading offset d moves an impulse at p to p - d, and the feature value
+    that multiplies it is the one at the node where the convolution's output
+    sits.  Only channel 1 of e is ever nonzero, so z = i e[1]."""
+    a0 = feats["a"][1][0]
+    s1 = feats["s"][1][1]
+    sub = lambda p, *ds: tuple(pi - sum(d[i] for d in ds) for i, pi in enumerate(p))
+    z = np.zeros(shape, dtype=complex)
+    # step 1 from e = 0: e1 = Wsm1 * (s (.) (KS * r1))
+    p1 = sub(x0, o["sS"])
+    q1 = sub(p1, o["s1"])
+    e1 = s1[p1]
+    z[q1] += 1j * e1
+    # step 2: t = r1 - W * e1 - a (.) (KA * e1) lives in channel 0
+    t = {x0: 1.0}
+    qa = sub(q1, o["sA"])
+    qw = sub(q1, o["sW"])
+    t[qa] = t.get(qa, 0.0) - a0[qa] * e1
+    t[qw] = t.get(qw, 0.0) - o["wW"] * e1
+    for p, v in t.items():
+        pu = sub(p, o["sS"])
+        z[sub(pu, o["s2"])] += 1j * s1[pu] * v
+    return z
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_feature_modulation_order_closed_form(dim):
+    """Eq. pyhs_conv: a physical feature modulates the OUTPUT of the linear
+    convolution, Phi = c (.) (K_x * x), in both the level operator A_l and the
+    smoother S_l (Sec. 3.2).  With spatially varying a_l, s_l and one-hot
+    off-centre kernels on distinct channel pairs, an impulse's image carries
+    the feature values at the convolutions' output nodes, not at their
+    source nodes."""
+    W, feats, shape, x0, o = _modulation_case(dim)
+    r = np.zeros(shape, dtype=complex)
+    r[x0] = 1.0
+    got = mcmg.vcycle(W, feats, r)
+    ref = _modulation_expected(feats, shape, x0, o)
+    assert np.count_nonzero(ref) == 4
+    assert np.abs(got - ref).max() <= 1e-15 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("which", ["level_op", "smoother"])
+def test_feature_modulation_order_rejects_swapped_oracle(which, monkeypatch):
+    """The closed-form pin above fails when the oracle modulates the input of
+    the convolution instead (K * (a (.) e) or K * (s (.) x)): planted in the
+    oracle, on the CPU."""
+    def level_op_swapped(wts, feats, l, e):
+        return oc.conv(e, wts("W", l)) + oc.conv(feats["a"][l] * e, wts("KA", l))
+
+    def smoother_swapped(wts, feats, l, i, x):
+        return oc.conv(oc.conv(feats["s"][l] * x, wts("KS", l)), wts("Wsm", l, i))
+
+    monkeypatch.setattr(mcmg, which, level_op_swapped if which == "level_op" else smoother_swapped)
+    W, feats, shape, x0, o = _modulation_case(2)
+    r = np.zeros(shape, dtype=complex)
+    r[x0] = 1.0
+    got = mcmg.vcycle(W, feats, r)
+    ref = _modulation_expected(feats, shape, x0, o)
+    assert np.abs(got - ref).max() > 1e-3 * np.abs(ref).max()
