@@ -75,7 +75,8 @@ typedef struct { const void* blob; size_t bytes; } mcmg_weights;
 
 typedef struct {
   int precision;   /* mcmg_precision of the V-cycle convolutions           */
-  int restart;     /* FGMRES restart length m (1..64; 0 selects 30)        */
+  int restart;     /* FGMRES restart length m (1..1024; 0 selects 30);
+                      batched solves and the server take m <= 64          */
   void* stream;    /* hipStream_t for all work; NULL = default stream      */
   int ortho;       /* 0: classical Gram-Schmidt with re-orthogonalisation
                       when the norm drops below 1/sqrt(2) (default);
@@ -118,6 +119,10 @@ mcmg_status mcmg_matvec(mcmg_handle h, const double* u, double* Au);
  * f: device rhs; u: device in/out (initial guess in, solution out).  Stops
  * when the FP64 true residual |f - A u| <= tol |f|, or after maxit
  * preconditioner applications (returns MCMG_NOT_CONVERGED with the best u).
+ * A Hessenberg column that is zero after the earlier rotations (for example
+ * MG(v_j) = 0) is left out of the cycle's triangular solve; when it is the
+ * first column of a cycle the solve returns MCMG_NOT_CONVERGED with u
+ * unchanged, since a restart would repeat the same cycle.
  * info may be NULL.  Blocks until done. */
 mcmg_status mcmg_solve(mcmg_handle h, const double* f, double* u, double tol,
                        int maxit, mcmg_info* info);

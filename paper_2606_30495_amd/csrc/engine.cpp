@@ -76,6 +76,7 @@ bool Engine::compatible(const Ctx* c, std::string* why) const {
   if (c->dim != dim_ || c->L != L_) return no("dimension and level count differ");
   if (c->precision != prec_) return no("precision differs");
   if (c->restart != m_ || c->ortho != ortho_) return no("restart length or orthogonalisation differs");
+  if (c->restart > 64) return no("batched solves take restart lengths up to 64");
   for (int l = 0; l < L_; ++l) {
     const Level& lv = c->lev[l];
     if (lv.C != C_[l] || lv.nu1 != nu1_[l] || lv.nu2 != nu2_[l]) return no("level structure differs");
@@ -439,13 +440,19 @@ mcmg_status Engine::complete(std::vector<Work*>* finished) {
         settle(w, g[4 * i + 3]);
         break;
       case Work::ITER: {
-        const double rho = g[4 * i], hn = g[4 * i + 1], cn = g[4 * i + 2];
+        const double rho = g[4 * i], hn = g[4 * i + 1], cn = g[4 * i + 2], diag = g[4 * i + 3];
         ++w->its;
         w->hist.push_back(rho / w->fnorm);
         w->relest = rho / w->fnorm;
         w->k = w->j + 1;
         if (!std::isfinite(rho) || !std::isfinite(hn)) {
           finish(w, fail(MCMG_E_NONFINITE, "non-finite value in the Arnoldi process"));
+        } else if (diag == 0.0) {
+          // column j is zero after the earlier rotations: close the cycle
+          // with the columns before it, or stop (u unchanged) when none is left
+          w->k = w->j;
+          if (w->k == 0) finish(w, MCMG_NOT_CONVERGED);
+          else w->st = Work::END;
         } else if (rho <= w->target || hn <= 1e-14 * cn || w->its >= w->maxit || w->j + 1 == m_) {
           w->st = Work::END;
         } else {

@@ -229,22 +229,29 @@ __device__ __forceinline__ void reduce_norm_body(const double* __restrict__ part
   }
 }
 
-// Largest restart length (the handle rejects longer ones): bounds the LDS
-// copies of the Hessenberg columns below.
+// Largest restart length whose back substitution stages the whole upper
+// triangle of H in LDS; the batched engine takes restarts up to this length.
 constexpr int KMAX = 64;
+// Largest restart length a handle takes (single-problem solves): bounds the
+// LDS copies of one Hessenberg column and of the right-hand side of the
+// triangular solve.
+constexpr int KMAX_LONG = 1024;
 
 // Givens step on column j of H (complex, column-major, ldh rows), by one
 // block: the threads copy the column and the stored rotations to LDS, one
 // thread applies the rotations there in order (each on the entry the
 // previous one produced) and computes the new one, and the threads write
 // the column back.  hn[0] may have been written by thread 0 of this block.
+// out = (|g_{j+1}|, h_{j+1,j}, |column j| before rotation, |new diagonal|);
+// a zero diagonal (a column that is zero after the earlier rotations) makes
+// column j unusable for the triangular solve, and the host leaves it out.
 __device__ __forceinline__ void givens_block(double* __restrict__ H, int ldh, int j,
                                              const double* hn, double* __restrict__ cs,
                                              double* __restrict__ sn, double* __restrict__ g,
                                              double* out) {
-  __shared__ double2 colS[KMAX + 1];
-  __shared__ double2 snS[KMAX];
-  __shared__ double csS[KMAX];
+  __shared__ double2 colS[KMAX_LONG + 1];
+  __shared__ double2 snS[KMAX_LONG];
+  __shared__ double csS[KMAX_LONG];
   double* __restrict__ col = H + 2LL * j * ldh;
   const int tid = threadIdx.x, nt = blockDim.x;
   for (int i = tid; i <= j; i += nt) colS[i] = make_double2(col[2 * i], col[2 * i + 1]);
@@ -297,6 +304,7 @@ __device__ __forceinline__ void givens_block(double* __restrict__ H, int ldh, in
     out[0] = hypot(g1r, g1i);
     out[1] = b;
     out[2] = cn;
+    out[3] = t;
   }
   __syncthreads();
   for (int i = tid; i <= j + 1; i += nt) {
@@ -305,16 +313,44 @@ __device__ __forceinline__ void givens_block(double* __restrict__ H, int ldh, in
   }
 }
 
-// y = H[0:k,0:k]^{-1} g[0:k] by back substitution, by one block: the
-// threads copy the upper triangle of H (packed by columns) and g to LDS, one
-// thread substitutes there (row k-1 first, each row's sum in column order),
-// and the threads write y.
+// y = H[0:k,0:k]^{-1} g[0:k] by back substitution, by one block.  Up to
+// KMAX columns the threads copy the upper triangle of H (packed by columns)
+// and g to LDS, one thread substitutes there (row k-1 first, each row's sum
+// in column order), and the threads write y.  Longer systems substitute by
+// columns: y_i = s_i / H_ii by one thread, then every thread removes
+// H_li y_i from its rows l < i of s (kept in LDS), reading H from global
+// memory; each row's sum then runs from column k-1 down.
 __device__ __forceinline__ void backsolve_block(const double* __restrict__ H, int ldh, int k,
                                                 const double* __restrict__ g,
                                                 double* __restrict__ y) {
   __shared__ double2 tri[KMAX * (KMAX + 1) / 2];
-  __shared__ double2 ys[KMAX];
+  __shared__ double2 ys[KMAX_LONG];
   const int tid = threadIdx.x, nt = blockDim.x;
+  if (k > KMAX) {
+    for (int i = tid; i < k; i += nt) ys[i] = make_double2(g[2 * i], g[2 * i + 1]);
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+      const double* col = H + 2LL * i * ldh;
+      if (tid == 0) {
+        const double dr = col[2 * i], di = col[2 * i + 1];
+        const double q = dr * dr + di * di;
+        const double sr = ys[i].x, si = ys[i].y;
+        ys[i] = make_double2((sr * dr + si * di) / q, (si * dr - sr * di) / q);
+      }
+      __syncthreads();
+      const double yr = ys[i].x, yi = ys[i].y;
+      for (int l = tid; l < i; l += nt) {
+        const double hr = col[2 * l], hi = col[2 * l + 1];
+        ys[l] = make_double2(ys[l].x - (hr * yr - hi * yi), ys[l].y - (hr * yi + hi * yr));
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < k; i += nt) {
+      y[2 * i] = ys[i].x;
+      y[2 * i + 1] = ys[i].y;
+    }
+    return;
+  }
   for (int l = 0; l < k; ++l) {
     const long long c = (long long)l * ldh;
     const int o = l * (l + 1) / 2;
@@ -419,8 +455,7 @@ __global__ void scale_kernel(const double* __restrict__ w, const double* __restr
 }
 
 __global__ void init_g_kernel(double* g, int m1, const double* beta) {
-  const int i = threadIdx.x;
-  if (i < m1) {
+  for (int i = threadIdx.x; i < m1; i += blockDim.x) {
     g[2 * i] = (i == 0) ? beta[0] : 0.0;
     g[2 * i + 1] = 0.0;
   }
@@ -539,6 +574,7 @@ __global__ __launch_bounds__(RB) void kb_givens(const KArgs* __restrict__ tab,
   gather[4 * p + 0] = A.scal[16];
   gather[4 * p + 1] = A.scal[17];
   gather[4 * p + 2] = A.scal[18];
+  gather[4 * p + 3] = A.scal[19];     // |new diagonal| (slot 3 holds |r| after a residual tick)
 }
 
 // mode 0: V_0 = r / |r|  (|r| in scal[3]);  mode 1: V_{j+1} = w / h_{j+1,j}
@@ -665,20 +701,20 @@ hipError_t launch_scale(const double* w, const double* hn, double* v, long long 
 hipError_t launch_norm_givens(const double* partial, int nb, const double* wnorm2, double* hn,
                               int* skip, double* H, int ldh, int j, double* cs, double* sn,
                               double* g, double* out, hipStream_t s) {
-  if (j < 0 || j >= KMAX) return hipErrorInvalidValue;
+  if (j < 0 || j >= KMAX_LONG) return hipErrorInvalidValue;
   hipLaunchKernelGGL(norm_givens_kernel, dim3(1), dim3(RB), 0, s, partial, nb, wnorm2, hn, skip, H,
                      ldh, j, cs, sn, g, out);
   return hipGetLastError();
 }
 
 hipError_t launch_init_g(double* g, int m1, const double* beta, hipStream_t s) {
-  hipLaunchKernelGGL(init_g_kernel, dim3(1), dim3(128), 0, s, g, m1, beta);
+  hipLaunchKernelGGL(init_g_kernel, dim3(1), dim3(256), 0, s, g, m1, beta);
   return hipGetLastError();
 }
 
 hipError_t launch_backsolve(const double* H, int ldh, int k, const double* g, double* y,
                             hipStream_t s) {
-  if (k < 0 || k > KMAX) return hipErrorInvalidValue;
+  if (k < 0 || k > KMAX_LONG) return hipErrorInvalidValue;
   hipLaunchKernelGGL(backsolve_kernel, dim3(1), dim3(64), 0, s, H, ldh, k, g, y);
   return hipGetLastError();
 }

@@ -474,7 +474,7 @@ mcmg_status do_setup(const double* c, mcmg_grid grid, double omega, double h, mc
   }
   if (ctx->precision != MCMG_FP32 && ctx->precision != MCMG_BF16)
     return fail(MCMG_E_ARG, "unknown precision %d", ctx->precision);
-  if (ctx->restart < 1 || ctx->restart > 64) return fail(MCMG_E_ARG, "restart must be 1..64");
+  if (ctx->restart < 1 || ctx->restart > 1024) return fail(MCMG_E_ARG, "restart must be 1..1024");
   double cmax = 0.0;
   for (long long i = 0; i < nint; ++i) {
     if (!std::isfinite(c[i])) return fail(MCMG_E_NONFINITE, "non-finite wave speed");

@@ -137,8 +137,9 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       HCK(launch_norm_givens(c->partial, nb, c->scal + 8, c->scal + 9, c->skip, c->H, ldh, j,
                              c->cs, c->sn, c->g, c->scal + 16, s));
       if (j + 1 < m) HCK(launch_scale(c->wv, c->scal + 9, c->V + 2LL * (j + 1) * N, N, s));
-      HCK(read_scal(c, 16, 3));
+      HCK(read_scal(c, 16, 4));
       const double rho = c->host_scal[0], hn = c->host_scal[1], cn = c->host_scal[2];
+      const double diag = c->host_scal[3];
       if (c->prof.on && c->prof.recs.size() >= 2) {
         // the second Gram-Schmidt pass did no work when the device skipped it
         int skipped = 0;
@@ -160,7 +161,19 @@ mcmg_status fgmres(Ctx* c, const double* f, double* u, double tol, int maxit, mc
       k = j + 1;
       if (!std::isfinite(rho) || !std::isfinite(hn))
         return fin.done(fail(MCMG_E_NONFINITE, "non-finite value in the Arnoldi process"));
+      if (diag == 0.0) {
+        // column j is zero after the earlier rotations (e.g. MG(v_j) = 0):
+        // the triangular system of the cycle is the j columns before it
+        k = j;
+        break;
+      }
       if (rho <= target || hn <= 1e-14 * cn || its >= maxit) break;
+    }
+    if (k == 0) {
+      // not even the first direction is usable: a restart would repeat this
+      // cycle, so stop with u unchanged
+      fin.iters = its;
+      return fin.done(MCMG_NOT_CONVERGED);
     }
     HCK(launch_backsolve(c->H, ldh, k, c->g, c->y, s));
     HCK(c->timed("zupdate_kernel", 8.0 * N * k, (8.0 * k + 32.0) * N,

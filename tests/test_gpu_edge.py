@@ -130,3 +130,57 @@ def test_born_zero_rhs_and_maxit_zero(method):
     assert np.array_equal(to_host(u), u0)
     true = np.linalg.norm(f - born.apply_periodic(op, u0)) / np.linalg.norm(f)
     assert abs(info["relres_true"] - true) <= 1e-12 * true
+
+
+def _zero_weight_problem():
+    """bump 32^2 + 6-cell PML with every weight tensor zero: MG(r) = 0 for
+    every r, so w = A MG(v_1) = 0 and the first Hessenberg column is zero."""
+    p = problem(2, 32, 6, (2, 8, 16))
+    L = len(p["channels"])
+    tens = [dict(t, w=np.zeros_like(t["w"])) for t in p["tens"]]
+    p["blob"] = synth.pack_blob(2, p["channels"], p["nu1"], p["nu2"], tens)
+    f = synth.point_source(32, 6, (0.5, 0.25), 2)
+    return p, f
+
+
+def test_zero_preconditioner_column_leaves_u_unchanged():
+    """A preconditioner that maps v_1 to zero gives a zero first column of H
+    (its rotated diagonal is zero): the cycle has no usable direction, so the
+    solve stops with NOT_CONVERGED after that one application, u unchanged
+    and finite, and the reported residual that of the initial guess."""
+    say("[edge-zero-mg]")
+    p, f = _zero_weight_problem()
+    op, _, _ = oracle_parts(p)
+    u0 = 1e-3 * synth.random_rhs(f.shape, 14)
+    H = handle(p)
+    u = to_dev(u0)
+    info = H.solve(to_dev(f), u, tol=1e-6, maxit=20)
+    H.close()
+    say(f"  status {info['status']} iters {info['iters']} relres {info['relres_true']:.3e}")
+    assert info["status"] == 1 and info["iters"] == 1
+    assert np.array_equal(to_host(u), u0)
+    true = np.linalg.norm(f - helmholtz.apply(op, u0)) / np.linalg.norm(f)
+    assert abs(info["relres_true"] - true) <= 1e-12 * true
+
+
+def test_zero_preconditioner_column_in_a_batch():
+    """The batched engine takes the same decision for a zero-MG problem
+    while an ordinary problem in the same batch runs on and equals its
+    single solve bitwise."""
+    from paper_2606_30495_amd import solve_batch
+    say("[edge-zero-mg-batch]")
+    p0, f0 = _zero_weight_problem()
+    p1 = problem(2, 32, 6, (2, 8, 16))
+    f1 = synth.point_source(32, 6, (0.3, 0.6), 2)
+    u0 = 1e-3 * synth.random_rhs(f0.shape, 15)
+    h0, h1 = handle(p0), handle(p1)
+    ua, ub = to_dev(u0), to_dev(np.zeros_like(f1))
+    st, infos = solve_batch([h0, h1], [to_dev(f0), to_dev(f1)], [ua, ub], tol=1e-6, maxit=12)
+    ref = to_dev(np.zeros_like(f1))
+    info1 = h1.solve(to_dev(f1), ref, tol=1e-6, maxit=12)
+    h0.close()
+    h1.close()
+    assert infos[0]["status"] == 1 and infos[0]["iters"] == 1
+    assert np.array_equal(to_host(ua), u0)
+    assert infos[1]["iters"] == info1["iters"] == 12
+    assert np.array_equal(to_host(ub), to_host(ref))

@@ -103,8 +103,8 @@ def test_server_results_equal_alone_with_arrivals_in_flight():
         assert c["iters_max"] == max(i["iters"] for _, i in ref)
         for (u_ref, _), u in zip(ref, ud):
             assert np.array_equal(to_host(u), u_ref)
-        if media[m]["dim"] == 2:
-            assert c["status"] == 0 and c["relres_max"] <= 1e-6
+        # 2D and 3D media alike reach the tolerance within the cap
+        assert c["status"] == 0 and c["relres_max"] <= 1e-6, (m, c)
     srv.close()
 
 
