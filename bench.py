@@ -1,7 +1,11 @@
 """Benchmark: FGMRES + McMg V-cycle iterations per second on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config grf1024]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config layered192]
                     [--precision fp32|bf16] [--no-cpu]
+
+The headline workload is the largest single-solve configuration: the 3D
+192^3 layered medium (216^3 extended, 5 levels 2/12/24/48/96, FGMRES(20)),
+with the V-cycle in FP32, the paper's preconditioner precision (Sec. 4.1).
 
 A step is one FGMRES iteration of the whole hot path: one V-cycle (lift,
 smoothing, restriction, coarsest level, prolongation, projection), one FP64
@@ -21,8 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-PEAK_FP32_TFLOPS = 157.3     # vector and matrix FP32
-PEAK_BF16_TFLOPS = 2500.0    # dense MFMA
+PEAK_FP32_MFMA_TFLOPS = 157.3   # dense FP32 matrix cores
+# FP32 vector rate without packed-FP32 instructions (the library is built
+# with them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz;
+# the 157.3 TFLOP/s vector figure needs packed FP32
+PEAK_FP32_VALU_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0       # dense MFMA
 PEAK_FP64_TFLOPS = 78.6
 # iteration cap of the serving leg: the classical stand-in coefficients need
 # 200-750 iterations on these media
@@ -34,8 +42,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="grf1024")
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--config", default="layered192")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--grf-steps", type=int, default=30,
+                    help="iterations of the 2D 1024^2 leg in each precision (0: skip)")
     ap.add_argument("--single", action="store_true", help="skip the other-precision leg")
     ap.add_argument("--solves", type=int, default=50,
                     help="right-hand sides of the solve-to-tolerance leg (0: skip)")
@@ -49,7 +59,11 @@ def parse():
     ap.add_argument("--train-steps", type=int, default=50,
                     help="Adam steps of the training leg (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3)
+    ap.add_argument("--cpu-iters", type=int, default=1,
+                    help="FGMRES iterations of the oracle sample")
+    ap.add_argument("--cpu-side", type=int, default=104,
+                    help="interior side of the oracle's reduced-grid sample of a 3D "
+                         "headline workload")
     return ap.parse_args()
 
 
@@ -62,11 +76,11 @@ def roofline_for(rec, precision):
     if name.startswith(("mconv_kernel<", "mstep_kernel<")) and ", true," in name:
         peak_fl, unit_bound = PEAK_BF16_TFLOPS, "mfma"
     elif name.startswith(("mconv_kernel", "mstep_kernel")):
-        peak_fl, unit_bound = PEAK_FP32_TFLOPS, "mfma"
+        peak_fl, unit_bound = PEAK_FP32_MFMA_TFLOPS, "mfma"
     elif name.startswith(("multidot", "update", "zupdate", "helm")):
         peak_fl, unit_bound = PEAK_FP64_TFLOPS, "alu"
     else:
-        peak_fl, unit_bound = PEAK_FP32_TFLOPS, "alu"
+        peak_fl, unit_bound = PEAK_FP32_VALU_TFLOPS, "alu"
     ridge = peak_fl * 1e12 / (PEAK_HBM_GBS * 1e9)
     intensity = fl / max(by, 1.0)
     if intensity < ridge:
@@ -88,7 +102,7 @@ def mfma_for(recs, precision, ms_per_step, iters):
     ms = sum(r["total_ms"] for r in mm)
     if not mm or ms <= 0:
         return None
-    peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP32_TFLOPS
+    peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP32_MFMA_TFLOPS
     ach = fl / (ms * 1e-3) / 1e12
     return {"kernels": "matrix-core convolutions (mconv_kernel, mstep_kernel)",
             "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
@@ -378,10 +392,32 @@ def traffic_for(kernel):
     return None
 
 
-def cpu_baseline(cfg, c, omega, h, f, tens, iters):
-    """The FP64 oracle on the host cores: setup + `iters` FGMRES iterations of
-    the same workload (a bounded sample of the solve)."""
+def _host_cpu():
+    """CPU model name and logical CPU count of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(cfg, iters, side):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload.
+
+    2D: setup + `iters` FGMRES iterations of the workload itself.  3D: one
+    oracle V-cycle at 216^3 takes minutes, so the sample is the same model,
+    medium recipe, ppw, PML and source at a reduced interior side `side`:
+    setup + `iters` FGMRES iterations, scaled to the full grid by node count
+    (every step of an iteration is linear in the node count) and labelled
+    extrapolated."""
+    import dataclasses
     import numpy as np
+    import synth
     from oracle import helmholtz, krylov, mcmg
     try:
         import threadpoolctl
@@ -390,29 +426,47 @@ def cpu_baseline(cfg, c, omega, h, f, tens, iters):
         threads = max(blas) if blas else 1
     except Exception:
         threads = 1
+    scfg = cfg if cfg.dim == 2 else dataclasses.replace(cfg, n=side)
+    c, omega, h, f = synth.make_problem(scfg)
+    tens = synth.make_weights(scfg.dim, scfg.channels, scfg.nu1, scfg.nu2, scfg.weight_seed)
     t0 = time.perf_counter()
-    op = helmholtz.setup_operator(c, omega, h, cfg.npml)
-    W = mcmg.Weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
+    op = helmholtz.setup_operator(c, omega, h, scfg.npml)
+    W = mcmg.Weights(scfg.dim, scfg.channels, scfg.nu1, scfg.nu2, tens)
     M = mcmg.Preconditioner(W, np.sqrt(op["k2"]), h)
     t1 = time.perf_counter()
-    _, info = krylov.fgmres(lambda x: helmholtz.apply(op, x), M, f, m=cfg.restart,
-                            tol=cfg.tol, maxit=iters)
+    _, info = krylov.fgmres(lambda x: helmholtz.apply(op, x), M, f, m=scfg.restart,
+                            tol=scfg.tol, maxit=iters)
     t2 = time.perf_counter()
-    return {"value": round(info["iters"] / (t2 - t1), 5), "unit": "iters/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{cfg.name}: oracle setup ({t1 - t0:.1f} s) then {info['iters']} FGMRES "
-                      f"iterations ({t2 - t1:.1f} s) from u=0; BLAS threads {threads}, NumPy "
-                      f"elementwise work single-threaded; host {os.cpu_count()} CPUs"}
+    scale = (scfg.n_ext / cfg.n_ext) ** cfg.dim
+    rate = info["iters"] / (t2 - t1) * scale
+    model, ncpu = _host_cpu()
+    if scfg is cfg:
+        what = f"{cfg.name}: oracle setup ({t1 - t0:.1f} s) then {info['iters']} FGMRES iterations " \
+               f"({t2 - t1:.1f} s) from u=0"
+    else:
+        what = (f"{cfg.name} model and medium recipe at {scfg.n}^3 interior + {scfg.npml}-cell PML "
+                f"({scfg.n_ext}^3 nodes): oracle setup ({t1 - t0:.1f} s) then {info['iters']} "
+                f"FGMRES iteration(s) ({t2 - t1:.1f} s) from u=0, extrapolated to {cfg.n_ext}^3 "
+                f"by node count (x{1 / scale:.2f})")
+    return {"value": round(rate, 6), "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "extrapolated": scfg is not cfg,
+            "sample": f"{what}; BLAS threads {threads}, NumPy elementwise work single-threaded; "
+                      f"host {model}, {ncpu} logical CPUs"}
 
 
-def born_leg(cfg, c, omega, h, f, blob, precision, iters):
-    """Born-series form on the same medium with a sponge layer of the same
-    width: Born+McMg (u <- u + MG(G(f - A_per u)), G by FFT) and CBS, each
-    run for `iters` steps from u = 0, plus the FFT passes' HIP-event timing.
-    The iteration count is fixed (random-init weights), so the leg measures
-    the cost per Born step."""
+def born_leg(iters, precision="bf16"):
+    """Born-series form (Born+McMg, u <- u + MG(G(f - A_per u)), G by FFT) on
+    the 2D 1024^2 GRF medium with a 16-cell sponge layer, run for `iters`
+    steps from u = 0, plus the FFT passes' HIP-event timing.  The iteration
+    count is fixed (random-init weights), so the leg measures the cost per
+    Born step."""
     import torch
+    import synth
     from paper_2606_30495_amd import Handle
+    cfg = synth.CONFIGS["grf1024"]
+    c, omega, h, f = synth.make_problem(cfg)
+    tens = synth.make_weights(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, cfg.weight_seed)
+    blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
     H = Handle(c, omega, h, cfg.npml, blob, precision=precision, restart=2, absorber="sponge")
     H.born_setup()
     k0sq, eps = H.born_params()
@@ -420,16 +474,15 @@ def born_leg(cfg, c, omega, h, f, blob, precision, iters):
     ud = torch.zeros_like(fd)
     out = {"workload": f"{cfg.name} with a {cfg.npml}-cell sponge layer, periodic Born operator",
            "precision": precision, "k0sq": k0sq, "eps": eps}
-    for method in ("mcmg", "cbs"):
-        H.born_solve(fd, ud, method=method, tol=1e-300, maxit=2, hist_cap=0)   # warm-up
-        ud.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = H.born_solve(fd, ud, method=method, tol=1e-300, maxit=iters, hist_cap=0)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[method] = {"iters_per_s": round(info["iters"] / el, 3),
-                       "ms_per_step": round(el / max(info["iters"], 1) * 1e3, 4)}
+    H.born_solve(fd, ud, method="mcmg", tol=1e-300, maxit=2, hist_cap=0)   # warm-up
+    ud.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = H.born_solve(fd, ud, method="mcmg", tol=1e-300, maxit=iters, hist_cap=0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["mcmg"] = {"iters_per_s": round(info["iters"] / el, 3),
+                   "ms_per_step": round(el / max(info["iters"], 1) * 1e3, 4)}
     ud.zero_()
     H.prof_enable(True)
     H.born_solve(fd, ud, method="mcmg", tol=1e-300, maxit=iters, hist_cap=0)
@@ -498,6 +551,17 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def workload_name(cfg):
+    side = "x".join([str(cfg.n_ext)] * cfg.dim)
+    return (f"{cfg.name}: {cfg.dim}D {cfg.n}^{cfg.dim} interior + {cfg.npml}-cell PML ({side}), "
+            f"{cfg.levels} levels {'/'.join(str(c) for c in cfg.channels)}, FGMRES({cfg.restart})")
+
+
+def leg_summary(leg):
+    return {"value": round(leg["value"], 3), "ms_per_step": round(leg["ms_per_step"], 4),
+            "relres_true": leg["info"]["relres_true"], "dominant_kernel": leg["recs"][0]["name"]}
+
+
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -514,11 +578,11 @@ def main():
     blob = synth.pack_blob(cfg.dim, cfg.channels, cfg.nu1, cfg.nu2, tens)
 
     head = run_leg(cfg, c, omega, h, f, blob, a.precision, a.steps, a.warmup)
-    progress(f"{a.precision} leg: {head['value']:.1f} iters/s")
+    progress(f"{cfg.name} {a.precision} leg: {head['value']:.1f} iters/s")
     other = "fp32" if a.precision == "bf16" else "bf16"
     cmp_leg = None if a.single else run_leg(cfg, c, omega, h, f, blob, other, a.steps, a.warmup)
     if cmp_leg is not None:
-        progress(f"{other} leg: {cmp_leg['value']:.1f} iters/s")
+        progress(f"{cfg.name} {other} leg: {cmp_leg['value']:.1f} iters/s")
     recs = head["recs"]
     dom = recs[0]
     roof = roofline_for(dom, a.precision)
@@ -533,10 +597,10 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if a.precision == "fp32" else "bf16",
         "data": "synthetic (seeded medium, random-init weights N(0,1/fan_in) seed 0)",
-        "config": {"workload": cfg.name, "dim": cfg.dim, "n_interior": cfg.n, "npml": cfg.npml,
-                   "n_ext": cfg.n_ext, "levels": cfg.levels, "channels": list(cfg.channels),
-                   "nu": [cfg.nu1[0], cfg.nu2[0]], "restart": cfg.restart,
-                   "precision": a.precision, "outer": "f64"},
+        "config": {"workload": workload_name(cfg), "dim": cfg.dim, "n_interior": cfg.n,
+                   "npml": cfg.npml, "n_ext": cfg.n_ext, "levels": cfg.levels,
+                   "channels": list(cfg.channels), "nu": [cfg.nu1[0], cfg.nu2[0]],
+                   "restart": cfg.restart, "precision": a.precision, "outer": "f64"},
         "solve": {"iters": head["iters"], "relres_true": head["info"]["relres_true"],
                   "converged": head["info"]["converged"], "setup_ms": round(head["setup_ms"], 2)},
         "roofline": roof,
@@ -544,31 +608,36 @@ def main():
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
                     for r in recs[:16]],
     }
+    if cmp_leg is not None:
+        line["compare"] = dict(precision=other, **leg_summary(cmp_leg))
+    if a.grf_steps > 0 and cfg.name != "grf1024":
+        g = synth.CONFIGS["grf1024"]
+        gc, gomega, gh, gf = synth.make_problem(g)
+        gt = synth.make_weights(g.dim, g.channels, g.nu1, g.nu2, g.weight_seed)
+        gb = synth.pack_blob(g.dim, g.channels, g.nu1, g.nu2, gt)
+        line["grf1024"] = {"workload": workload_name(g)}
+        for prec in ("fp32", "bf16"):
+            leg = run_leg(g, gc, gomega, gh, gf, gb, prec, a.grf_steps, a.warmup)
+            line["grf1024"][prec] = leg_summary(leg)
+        progress("grf1024 legs done")
     if a.solves > 0:
-        line["solves"] = [solves_leg(a.precision, a.solves)]
-        if not a.single:
-            line["solves"].append(solves_leg(other, a.solves))
+        line["solves"] = [solves_leg(p, a.solves) for p in ("bf16", "fp32")]
         progress("solve-to-tolerance legs done")
     if a.batched_iters > 0:
-        line["batched"] = batched_leg(a.precision, a.batched_iters)
+        line["batched"] = batched_leg("bf16", a.batched_iters)
         progress("batched leg done")
     if a.serve_requests > 0:
         line["served"] = served_leg(a.serve_requests, a.serve_rate)
         progress("served leg done")
-    if a.born_iters > 0 and cfg.dim == 2:
-        line["born"] = born_leg(cfg, c, omega, h, f, blob, a.precision, a.born_iters)
+    if a.born_iters > 0:
+        line["born"] = born_leg(a.born_iters)
         progress("Born leg done")
     if a.train_steps > 0:
         line["train"] = train_leg(a.train_steps)
         progress("training leg done")
-    if cmp_leg is not None:
-        line["compare"] = {"precision": other, "value": round(cmp_leg["value"], 3),
-                           "ms_per_step": round(cmp_leg["ms_per_step"], 4),
-                           "relres_true": cmp_leg["info"]["relres_true"],
-                           "dominant_kernel": cmp_leg["recs"][0]["name"]}
     if not a.no_cpu:
         progress("CPU oracle baseline ...")
-        line["cpu_baseline"] = cpu_baseline(cfg, c, omega, h, f, tens, a.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(cfg, a.cpu_iters, a.cpu_side)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
