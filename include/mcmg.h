@@ -111,6 +111,18 @@ mcmg_status mcmg_setup(const double* c, mcmg_grid grid, double omega, double h,
  * grid; may not alias.  Asynchronous on the handle's stream. */
 mcmg_status mcmg_apply(mcmg_handle h, const double* r, double* z);
 
+/* z = MG(r) like mcmg_apply, for callers that cannot allocate device memory
+ * (code under stream capture, serving loops that forbid hipMalloc): the
+ * V-cycle's level state lives in a static device array of the library
+ * (64 MiB on every GPU the library runs on, held until the process ends)
+ * instead of the handle's buffers.  Same kernels and summation order as
+ * mcmg_apply, so the same bits.  Allocates nothing (device or host); the
+ * array's device address is looked up once per device.  A grid whose level
+ * state needs more than 64 MiB is refused with MCMG_E_ARG.  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or threads) race.  Asynchronous on the handle's stream. */
+mcmg_status mcmg_apply_noalloc(mcmg_handle h, const double* r, double* z);
+
 /* Au = A u in FP64 (Eq. FDM_stencil with the PML of App. A.1.1).  u, Au:
  * device complex128 on the extended grid; may not alias.  Asynchronous. */
 mcmg_status mcmg_matvec(mcmg_handle h, const double* u, double* Au);

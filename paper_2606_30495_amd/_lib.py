@@ -85,6 +85,7 @@ EXPORTS = {
                                   ctypes.c_double, Pml, Weights, ctypes.POINTER(Opts),
                                   ctypes.POINTER(ctypes.c_void_p)]),
     "mcmg_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mcmg_apply_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mcmg_matvec": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mcmg_solve": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(Info)]),
@@ -234,6 +235,12 @@ class Handle:
     def apply(self, r, z):
         self._shape_check(r, z)
         _check(lib().mcmg_apply(self.ptr, _ptr(r), _ptr(z)))
+
+    def apply_noalloc(self, r, z):
+        """z = MG(r) with the level state in the library's static device
+        array (mcmg_apply_noalloc): no allocation."""
+        self._shape_check(r, z)
+        _check(lib().mcmg_apply_noalloc(self.ptr, _ptr(r), _ptr(z)))
 
     def matvec(self, u, Au):
         self._shape_check(u, Au)
