@@ -45,8 +45,10 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
 // Padded sizes of the packed operands (see conv_mfma.hip for the layout).
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
                     int* npairs, int* nsteps);
+// LDS of one block: the staged input tile plus the weight chunk, two chunk
+// buffers when the nsteps K-steps take more than one chunk.
 size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
-                      int kchunk);
+                      int kchunk, int nsteps);
 // Whether a tile (mt, ntw, rpw) is instantiated for this dim / epilogue.
 bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw);
 hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s);

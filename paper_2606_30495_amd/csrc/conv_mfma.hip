@@ -104,7 +104,7 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
 }
 
 size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
-                      int kchunk) {
+                      int kchunk, int nsteps) {
   int TX, TY, TZ;
   mfma_tile(dim, mt, rpw, &TX, &TY, &TZ);
   auto ext = [&](int t) { return mode == CONV_S1 ? t + 2 : (mode == CONV_S2 ? 2 * t + 1 : t + 1); };
@@ -112,8 +112,10 @@ size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int
   const int es = bf16 ? 2 : 4, kv = bf16 ? 8 : 1, ks = kchunk;
   const size_t stride = cinp + (bf16 ? 8 : 1);
   const size_t a = ((nodes * stride * es + 15) / 16) * 16;
+  // 3D float32 reads its B fragments from global memory: no weight chunk
+  if (!bf16 && dim == 3) return a;
   const size_t b = (size_t)(epi == EPI_RESID ? 2 : 1) * 4 * ks * ntw * 16 * kv * es;
-  return a + b;
+  return a + (kchunk < nsteps ? 2 : 1) * b;
 }
 
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,

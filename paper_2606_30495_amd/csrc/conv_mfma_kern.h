@@ -116,15 +116,43 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     const int row = rem / V16, vv = rem % V16;
     return (a ? wB : wA) + (((size_t)(4 * s0 + row) * ncols + col0) * KV) * ES + (size_t)vv * 16;
   };
-  auto wfetch = [&](int s0, int ks) {
+  auto wfetch = [&](int s0, int ks, unsigned char* dst) {
     const int total = NACC * 4 * ks * V16;
     for (int base = wave * 64; base < total; base += 256) {
       const int idx = base + lane;
-      if (idx < total) lds_copy16(wsrc(s0, ks, idx), bsm + (size_t)__builtin_amdgcn_readfirstlane(base) * 16);
+      if (idx < total) lds_copy16(wsrc(s0, ks, idx), dst + (size_t)__builtin_amdgcn_readfirstlane(base) * 16);
     }
   };
+  // Several chunks are double-buffered: chunk c sits in buffer c % 2, and
+  // chunk c + 1 is copied into the other buffer while chunk c is consumed.
+  // 3D float32: the B fragments come straight from the packed weights in
+  // global memory (L2-resident), so nothing but the input tile is staged
+  // and more blocks fit a CU; the first two groups of steps are requested
+  // before the staging.  (2D float32, with short K loops on small grids, is
+  // faster with the weights staged in LDS.)
+  constexpr bool BG = !BF && D == 3;
+  const size_t cbytes = (size_t)NACC * 4 * kchunk * BROW * ES;
   const int ks0 = nsteps < kchunk ? nsteps : kchunk;
-  wfetch(0, ks0);
+  if constexpr (!BG) wfetch(0, ks0, bsm);
+  constexpr int GS = 4;   // K steps per group of B loads (float32)
+  float bq0[GS][NACC][NTW], bq1[GS][NACC][NTW];   // unused unless BG
+  auto loadB = [&](int s0, float (&b)[GS][NACC][NTW]) {
+    const gptr<const float> wAf = (gptr<const float>)wA, wBf = (gptr<const float>)wB;
+#pragma unroll
+    for (int g = 0; g < GS; ++g) {
+      // steps past the end re-read the last one and are never multiplied
+      const int ss = (s0 + g) < nsteps ? (s0 + g) : nsteps - 1;
+#pragma unroll
+      for (int aa = 0; aa < NACC; ++aa)
+#pragma unroll
+        for (int t = 0; t < NTW; ++t)
+          b[g][aa][t] = (aa ? wBf : wAf)[(size_t)(4 * ss + lg) * ncols + col0 + t * 16 + li];
+    }
+  };
+  if constexpr (BG) {
+    loadB(0, bq0);
+    if (GS < nsteps) loadB(GS, bq1);
+  }
 
   // ---- stage the input tile: loads are issued in batches of SB per thread
   // before any LDS store, so a block waits for one memory latency per batch
@@ -249,11 +277,13 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     }
   }
   // Small tiles (used on small grids, where a block's latency is the
-  // launch's) read the fragments of step ss + 1 before the products of step
-  // ss are issued (two register sets), so LDS latency overlaps the matrix
-  // cores; larger tiles keep one set, for occupancy.  Every accumulator
-  // takes the steps in order.  Steps are loaded in order, so the pair walk
+  // launch's) and every float32 tile (one fragment is one register there)
+  // read the fragments of step ss + 1 before the products of step ss are
+  // issued (two register sets), so LDS latency overlaps the matrix cores;
+  // larger bf16 tiles keep one set, for occupancy.  Every accumulator takes
+  // the steps in order.  Steps are loaded in order, so the pair walk
   // advances once per load.
+  constexpr bool PIPE = PREF || !BF;
   PairWalk pw;
   pw.init(lg, cpv, npairs);
   typedef typename std::conditional<BF, bf16x8, float>::type Frag;
@@ -270,15 +300,14 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
             else acc[a][i][m][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][m], bf[a][t], acc[a][i][m][t], 0, 0, 0);
           }
   };
-  for (int s0 = 0; s0 < nsteps; s0 += KS) {
-    const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
-    if (s0 > 0) {
-      __syncthreads();   // previous chunk consumed
-      wfetch(s0, ks);
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-    }
-    auto load = [&](int ss, Frag (&bf)[NACC][NTW], Frag (&af)[RPW][MT]) {
+  if constexpr (BG) {
+    // float32: B fragments from global memory in groups of GS steps, two
+    // register sets: group g sits in set g % 2, and group g + 2 is loaded
+    // into that set as soon as group g has been multiplied, so each load has
+    // two groups of products to land (the first two are issued before the
+    // input tile is staged).  A fragments come from the staged tile, one
+    // step ahead.  No barrier inside the K loop.
+    auto loadA = [&](Frag (&af)[RPW][MT]) {
       int tap, cb;
       pw.take(tap, cb);
       int dz = 0, dy, dx;
@@ -286,39 +315,91 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
       else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
       const int aoff = ((dz * G::HY + dy) * G::HX + dx) * stride + cb * KV;
 #pragma unroll
-      for (int a = 0; a < NACC; ++a)
-#pragma unroll
-        for (int t = 0; t < NTW; ++t) {
-          const size_t o = ((size_t)a * 4 * ks + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
-          if constexpr (BF) bf[a][t] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(bsm) + o);
-          else bf[a][t] = reinterpret_cast<const float*>(bsm)[o];
-        }
-#pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-          if constexpr (BF) af[i][m] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) + abase[i][m] + aoff);
-          else af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
-        }
+        for (int m = 0; m < MT; ++m) af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
     };
-    Frag b0[NACC][NTW], a0[RPW][MT];
-    if constexpr (PREF) {
-      Frag b1[NACC][NTW], a1[RPW][MT];
-      load(0, b0, a0);
-      int ss = 0;
-      for (; ss + 1 < ks; ss += 2) {
-        load(ss + 1, b1, a1);
-        mma(b0, a0);
-        if (ss + 2 < ks) load(ss + 2, b0, a0);
-        mma(b1, a1);
+    Frag a0[RPW][MT], a1[RPW][MT];
+    loadA(a0);
+    // the products of one group (A fragments alternate a0 / a1: GS is even)
+    auto group = [&](int s0, const float (&b)[GS][NACC][NTW]) {
+#pragma unroll
+      for (int g = 0; g < GS; ++g) {
+        const int ss = s0 + g;
+        if (ss < nsteps) {
+          if ((g & 1) == 0) {
+            if (ss + 1 < nsteps) loadA(a1);
+            mma(b[g], a0);
+          } else {
+            if (ss + 1 < nsteps) loadA(a0);
+            mma(b[g], a1);
+          }
+        }
       }
-      if (ss < ks) mma(b0, a0);
-    } else {
-      for (int ss = 0; ss < ks; ++ss) {
-        load(ss, b0, a0);
-        mma(b0, a0);
+    };
+    for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
+      group(s0, bq0);
+      if (s0 + 2 * GS < nsteps) loadB(s0 + 2 * GS, bq0);
+      if (s0 + GS < nsteps) {
+        group(s0 + GS, bq1);
+        if (s0 + 3 * GS < nsteps) loadB(s0 + 3 * GS, bq1);
       }
     }
+  } else {
+    for (int s0 = 0, chunk = 0; s0 < nsteps; s0 += KS, ++chunk) {
+      const int ks = (nsteps - s0) < KS ? (nsteps - s0) : KS;
+      const unsigned char* cur = bsm + (chunk & 1) * cbytes;
+      const bool more = s0 + KS < nsteps;
+      // the other buffer was released by the barrier that ended the previous
+      // chunk, so the next chunk's copy can start before this one is used
+      if (more) wfetch(s0 + KS, (nsteps - s0 - KS) < KS ? (nsteps - s0 - KS) : KS, bsm + ((chunk + 1) & 1) * cbytes);
+      auto load = [&](int ss, Frag (&bf)[NACC][NTW], Frag (&af)[RPW][MT]) {
+        int tap, cb;
+        pw.take(tap, cb);
+        int dz = 0, dy, dx;
+        if (D == 2) { dy = tap / G::W; dx = tap % G::W; }
+        else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
+        const int aoff = ((dz * G::HY + dy) * G::HX + dx) * stride + cb * KV;
+  #pragma unroll
+        for (int a = 0; a < NACC; ++a)
+  #pragma unroll
+          for (int t = 0; t < NTW; ++t) {
+            const size_t o = ((size_t)a * 4 * ks + 4 * ss + lg) * BROW + (t * 16 + li) * KV;
+            if constexpr (BF) bf[a][t] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(cur) + o);
+            else bf[a][t] = reinterpret_cast<const float*>(cur)[o];
+          }
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i)
+  #pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            if constexpr (BF) af[i][m] = *reinterpret_cast<const bf16x8*>(reinterpret_cast<const u16*>(smem) + abase[i][m] + aoff);
+            else af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
+          }
+      };
+      Frag b0[NACC][NTW], a0[RPW][MT];
+      if constexpr (PIPE) {
+        Frag b1[NACC][NTW], a1[RPW][MT];
+        load(0, b0, a0);
+        int ss = 0;
+        for (; ss + 1 < ks; ss += 2) {
+          load(ss + 1, b1, a1);
+          mma(b0, a0);
+          if (ss + 2 < ks) load(ss + 2, b0, a0);
+          mma(b1, a1);
+        }
+        if (ss < ks) mma(b0, a0);
+      } else {
+        for (int ss = 0; ss < ks; ++ss) {
+          load(ss, b0, a0);
+          mma(b0, a0);
+        }
+      }
+      if (more) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies of the next chunk
+        __syncthreads();                                   // next chunk published, this one released
+      }
+    }
+
   }
 
   // ---- epilogue: per (row, m) the operands of all its outputs are loaded
@@ -386,7 +467,8 @@ hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
     return hipErrorInvalidValue;
   } else {
     const int nslices = a.ncols / (16 * NTW);
-    const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.rpw, a.cinp, a.epi, a.kchunk);
+    const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.rpw, a.cinp, a.epi, a.kchunk,
+                                      a.nsteps);
     if (b) {
       hipLaunchKernelGGL((mconv_kernel_batched<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(b->total, nslices),
                          dim3(256), lds, s, (const MArgs*)b->tab, b->pre, b->np, b->frozen, b->row);

@@ -39,7 +39,7 @@ namespace {
 template <int D> struct G1;
 template <> struct G1<2> { static constexpr int TZ = 1, TY = 8, TX = 64; };
 // 3D z-streaming tile: TY x TX nodes per plane, ZC planes per block
-struct G3 { static constexpr int TY = 8, TX = 64, ZC = 32; };
+struct G3 { static constexpr int TY = 8, TX = 60, ZC = 32; };
 
 constexpr int NTH = 256;
 
@@ -248,28 +248,42 @@ __device__ __forceinline__ void stage_weights(const L1Weights* __restrict__ src,
 // Ring slot of plane `pl` (pl >= -4 R) in a ring of R planes.
 __device__ __forceinline__ int ring(int pl, int R) { return (pl + 4 * R) % R; }
 
+// The z-march scatters every plane once: when plane k of a convolution's
+// input is in LDS, each point reads its 9 in-plane taps there and adds them,
+// with the dz = 2, 1, 0 weights, to the three outputs k - 1, k, k + 1 it
+// feeds (accumulator slots 0, 1, 2 of the thread's points).  Output k - 1
+// is then complete: it is finished, written, and the slots shift down by
+// one.  An output still takes its contributions plane by plane (dz = 0, 1,
+// 2) and tap by tap in row-major order, the order of a direct 27-tap sum,
+// but every staged value is read from LDS once instead of three times.
+// The weights come by value as a kernel argument (single problem: scalar
+// loads from the argument segment) or staged in LDS (batched launches).
 template <int VAR>
-__device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __restrict__ wp,
-                                         const int vblk) {
+__device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, const int vblk) {
   constexpr int TY = G3::TY, TX = G3::TX, ZC = G3::ZC;
-  constexpr int H = (VAR == L1_RESID) ? 1 : 3;           // y-x halo of the staged e
+  constexpr bool STEP = VAR == L1_STEP, FIRST = VAR == L1_FIRST, RESID = VAR == L1_RESID;
+  // e box (STEP: halo 3 around the tile; RESID: halo 1); FIRST has e = 0
+  constexpr int H = RESID ? 1 : 3;
   constexpr int EY = TY + 2 * H, EX = TX + 2 * H, NE = EY * EX;
-  constexpr int NER = (VAR == L1_STEP) ? 4 : 3;          // e ring (STEP keeps e of the output plane)
-  constexpr int TYt = TY + 4, TXt = TX + 4, NT = TYt * TXt;
+  // e planes held: STEP keeps k - 3 .. k + 1 (the output plane's e and the
+  // next plane being stored); RESID keeps k and k + 1
+  constexpr int NER = STEP ? 5 : 2;
+  // t box (halo 2) for STEP / FIRST; RESID computes t on the tile
+  constexpr int TYt = RESID ? TY : TY + 4, TXt = RESID ? TX : TX + 4, NT = TYt * TXt;
   constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
   constexpr int NO = TY * TX;
   constexpr int PE = (NE + NTH - 1) / NTH, PT = (NT + NTH - 1) / NTH;
   constexpr int PU = (NU + NTH - 1) / NTH, PO = (NO + NTH - 1) / NTH;
-  __shared__ float2 se[(VAR == L1_FIRST) ? 1 : NER * NE];
-  __shared__ float2 st[(VAR == L1_RESID) ? 1 : 3 * NT];
-  __shared__ float2 su[(VAR == L1_RESID) ? 1 : 3 * NU];
+  __shared__ float2 se[FIRST ? 1 : NER * NE];
+  __shared__ float2 st[RESID ? 1 : NT];      // t plane (FIRST: r plane) on the t box
+  __shared__ float2 su[RESID ? 1 : NU];      // u plane on the u box
 
   const gptr<const float2> __restrict__ e = to_global<const float2>(A.e);
   const gptr<float2> __restrict__ eo = to_global<float2>(A.eo);
   const gptr<const float2> __restrict__ r = to_global<const float2>(A.r);
   const gptr<const float2> __restrict__ a = to_global<const float2>(A.a);
   const gptr<const float2> __restrict__ s = to_global<const float2>(A.s);
-  const gptr<const L1Weights> wg = to_global<const L1Weights>(wp);
+  const L1Weights* wg = &wt;
   const int NZ = A.n.n[0], NY = A.n.n[1], NX = A.n.n[2];
   const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
   const int per = (ntiles + 7) / 8;
@@ -284,211 +298,259 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights* __res
   auto gidx = [&](int z, int y, int x) { return ((long long)z * NY + y) * NX + x; };
   const float2 zero = make_float2(0.f, 0.f);
 
-  // e plane k on the e box (zero outside the grid)
-  auto load_e = [&](int k) {
-    float2 v[PE];
-#pragma unroll
-    for (int j = 0; j < PE; ++j) {
-      const int i = threadIdx.x + j * NTH;
-      const int y = i / EX, x = i % EX;
-      const int gy = y0 - H + y, gx = x0 - H + x;
-      v[j] = ldz(e, gidx(k, gy, gx), i < NE && inside(k, gy, gx));
-    }
-    float2* dst = se + ring(k, NER) * NE;
-#pragma unroll
-    for (int j = 0; j < PE; ++j) {
-      const int i = threadIdx.x + j * NTH;
-      if (i < NE) dst[i] = v[j];
-    }
-  };
-  // acc += (X * src)[point] over the 27 taps, src planes q-1, q, q+1 in a ring
-  // (2 x 2 channel block X of the weight set `off` = W, KA, KS or Wsm).
-  auto conv2 = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
-                   gptr<const float> Xw, const int* base, float* c0, float* c1, auto npts) {
+  // Scatter plane P (pitch = its box width) into the accumulators of the
+  // outputs one behind (slot 0, dz = 2), level (slot 1, dz = 1) and one
+  // ahead (slot 2, dz = 0) of it; X holds the 2 x 2 channel block of one
+  // weight tensor, Y (when PAIR) a second one read from the same values.
+  auto scatter = [&](auto pair, const float2* P, int pitch, const float* Xw, const float* Yw,
+                     const int* base, auto& c0, auto& c1, auto& d0, auto& d1, auto npts) {
+    constexpr bool PAIR = decltype(pair)::value;
     constexpr int NP = decltype(npts)::value;
+    // taps at run time: only one tap's 12 (24) weights are live
 #pragma unroll 1
-    for (int dz = 0; dz < 3; ++dz) {
-      const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
-      const gptr<const float> w = Xw + dz * 9;
+    for (int t = 0; t < 9; ++t) {
+      const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
+      float2 v[NP];
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
+      for (int k = 0; k < NP; ++k) v[k] = P[base[k] + to];
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz) {
+        const int slot = 2 - dz;
+        const float* w = Xw + dz * 9;
         const float a00 = w[t], a01 = w[27 + t], a10 = w[54 + t], a11 = w[81 + t];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-          const float2 v = P[base[k] + to];
-          c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
-          c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
+          c0[slot][k] = fmaf(a00, v[k].x, fmaf(a01, v[k].y, c0[slot][k]));
+          c1[slot][k] = fmaf(a10, v[k].x, fmaf(a11, v[k].y, c1[slot][k]));
+        }
+        if constexpr (PAIR) {
+          const float* y = Yw + dz * 9;
+          const float b00 = y[t], b01 = y[27 + t], b10 = y[54 + t], b11 = y[81 + t];
+#pragma unroll
+          for (int k = 0; k < NP; ++k) {
+            d0[slot][k] = fmaf(b00, v[k].x, fmaf(b01, v[k].y, d0[slot][k]));
+            d1[slot][k] = fmaf(b10, v[k].x, fmaf(b11, v[k].y, d1[slot][k]));
+          }
         }
       }
     }
   };
-  // as conv2 for two weight sets X (into c0, c1) and Y (into d0, d1) that read
-  // each staged value once; every accumulator sums its taps in conv2's order
-  auto conv2pair = [&](const float2* ring_base, int R, int plane_elems, int q, int pitch,
-                       gptr<const float> Xw, gptr<const float> Yw, const int* base, float* c0, float* c1,
-                       float* d0, float* d1, auto npts) {
-    constexpr int NP = decltype(npts)::value;
-#pragma unroll 1
-    for (int dz = 0; dz < 3; ++dz) {
-      const float2* P = ring_base + ring(q - 1 + dz, R) * plane_elems;
-      const gptr<const float> w = Xw + dz * 9;
-      const gptr<const float> y = Yw + dz * 9;
+  // slot 0 is finished: move the others down, clear the new one ahead
+  auto shift = [&](auto& c) {
+    constexpr int NP = sizeof(c[0]) / sizeof(float);
 #pragma unroll
-      for (int t = 0; t < 9; ++t) {
-        const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
-        const float a00 = w[t], a01 = w[27 + t], a10 = w[54 + t], a11 = w[81 + t];
-        const float b00 = y[t], b01 = y[27 + t], b10 = y[54 + t], b11 = y[81 + t];
+    for (int k = 0; k < NP; ++k) {
+      c[0][k] = c[1][k];
+      c[1][k] = c[2][k];
+      c[2][k] = 0.f;
+    }
+  };
+  using std::integral_constant;
+
+  // ---- per-thread points of each box, fixed for the whole march ----------
+  // t box
+  int tb[PT], ty_[PT], tx_[PT];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-          const float2 v = P[base[k] + to];
-          c0[k] = fmaf(a00, v.x, fmaf(a01, v.y, c0[k]));
-          c1[k] = fmaf(a10, v.x, fmaf(a11, v.y, c1[k]));
-          d0[k] = fmaf(b00, v.x, fmaf(b01, v.y, d0[k]));
-          d1[k] = fmaf(b10, v.x, fmaf(b11, v.y, d1[k]));
-        }
+  for (int k = 0; k < PT; ++k) {
+    const int i = threadIdx.x + k * NTH;
+    ty_[k] = i / TXt;
+    tx_[k] = i % TXt;
+    // LDS base of tap (0, 0) in the e box (RESID / STEP)
+    tb[k] = (i < NT) ? (ty_[k] + H - (RESID ? 0 : 2)) * EX + (tx_[k] + H - (RESID ? 0 : 2)) : EX + 1;
+  }
+  // u box
+  int ub[PU], uy_[PU], ux_[PU];
+#pragma unroll
+  for (int k = 0; k < PU; ++k) {
+    const int i = threadIdx.x + k * NTH;
+    uy_[k] = i / UX;
+    ux_[k] = i % UX;
+    ub[k] = (i < NU) ? (uy_[k] + 1) * TXt + (ux_[k] + 1) : TXt + 1;
+  }
+  // output tile
+  int ob[PO], oy_[PO], ox_[PO];
+#pragma unroll
+  for (int k = 0; k < PO; ++k) {
+    const int i = threadIdx.x + k * NTH;
+    oy_[k] = i / TX;
+    ox_[k] = i % TX;
+    ob[k] = (i < NO) ? (oy_[k] + 1) * UX + (ox_[k] + 1) : UX + 1;
+  }
+
+  // ---- the arriving plane's operands, loaded one iteration ahead ---------
+  // STEP / RESID: e plane on the e box; FIRST: r plane on the t box
+  constexpr int PIN = FIRST ? PT : PE;
+  float2 vin[PIN];
+  auto load_in = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < PIN; ++j) {
+      if constexpr (FIRST) {
+        const int gy = y0 - 2 + ty_[j], gx = x0 - 2 + tx_[j];
+        const bool ok = threadIdx.x + j * NTH < NT && inside(k, gy, gx);
+        vin[j] = ldz(r, gidx(k, gy, gx), ok);
+      } else {
+        const int i = threadIdx.x + j * NTH;
+        const int gy = y0 - H + i / EX, gx = x0 - H + i % EX;
+        const bool ok = i < NE && inside(k, gy, gx);
+        vin[j] = ldz(e, gidx(k, gy, gx), ok);
       }
     }
   };
-  // t plane q on the t box (halo 2): t = r - W*e - a (.) (KA*e); FIRST: t = r
-  auto make_t = [&](int q) {
-    float2 rv[PT], av[PT];
-    int eb[PT];
-    bool ok[PT];
+  auto store_in = [&](int k) {
+    float2* dst = FIRST ? st : se + ring(k, NER) * NE;
+    constexpr int NB = FIRST ? NT : NE;
 #pragma unroll
-    for (int k = 0; k < PT; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int y = i / TXt, x = i % TXt;
-      const int gy = y0 - 2 + y, gx = x0 - 2 + x;
-      ok[k] = i < NT && inside(q, gy, gx);
-      rv[k] = ldz(r, gidx(q, gy, gx), ok[k]);
-      av[k] = (VAR != L1_FIRST) ? ldz(a, gidx(q, gy, gx), ok[k]) : zero;
-      eb[k] = (i < NT) ? (y + H - 2) * EX + (x + H - 2) : EX + 1;
-    }
-    float w0[PT], w1[PT], k0[PT], k1[PT];
-#pragma unroll
-    for (int k = 0; k < PT; ++k) w0[k] = w1[k] = k0[k] = k1[k] = 0.f;
-    if (VAR != L1_FIRST)
-      conv2pair(se, NER, NE, q, EX, &wg->W[0][0][0], &wg->KA[0][0][0], eb, w0, w1, k0, k1,
-                std::integral_constant<int, PT>());
-    float2* dst = st + ring(q, 3) * NT;
-#pragma unroll
-    for (int k = 0; k < PT; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      if (i < NT)
-        dst[i] = ok[k] ? make_float2(rv[k].x - w0[k] - av[k].x * k0[k], rv[k].y - w1[k] - av[k].y * k1[k])
-                       : zero;
-    }
-  };
-  // u plane p on the u box (halo 1): u = s (.) (KS * t)
-  auto make_u = [&](int p) {
-    float2 sv[PU];
-    int tb[PU];
-    bool ok[PU];
-#pragma unroll
-    for (int k = 0; k < PU; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int y = i / UX, x = i % UX;
-      const int gy = y0 - 1 + y, gx = x0 - 1 + x;
-      ok[k] = i < NU && inside(p, gy, gx);
-      sv[k] = ldz(s, gidx(p, gy, gx), ok[k]);
-      tb[k] = (i < NU) ? (y + 1) * TXt + (x + 1) : TXt + 1;
-    }
-    float c0[PU], c1[PU];
-#pragma unroll
-    for (int k = 0; k < PU; ++k) c0[k] = c1[k] = 0.f;
-    conv2(st, 3, NT, p, TXt, &wg->KS[0][0][0], tb, c0, c1, std::integral_constant<int, PU>());
-    float2* dst = su + ring(p, 3) * NU;
-#pragma unroll
-    for (int k = 0; k < PU; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      if (i < NU) dst[i] = ok[k] ? make_float2(sv[k].x * c0[k], sv[k].y * c1[k]) : zero;
-    }
-  };
-  // output plane z: e' = e + Wsm * u
-  auto make_out = [&](int z) {
-    int ub[PO];
-    bool ok[PO];
-#pragma unroll
-    for (int k = 0; k < PO; ++k) {
-      const int i = threadIdx.x + k * NTH;
-      const int y = i / TX, x = i % TX;
-      ok[k] = i < NO && inside(z, y0 + y, x0 + x);
-      ub[k] = (i < NO) ? (y + 1) * UX + (x + 1) : UX + 1;
-    }
-    float c0[PO], c1[PO];
-#pragma unroll
-    for (int k = 0; k < PO; ++k) c0[k] = c1[k] = 0.f;
-    conv2(su, 3, NU, z, UX, &wg->Wsm[0][0][0], ub, c0, c1, std::integral_constant<int, PO>());
-#pragma unroll
-    for (int k = 0; k < PO; ++k) {
-      if (!ok[k]) continue;
-      const int i = threadIdx.x + k * NTH;
-      const int y = i / TX, x = i % TX;
-      float2 ev = zero;
-      if (VAR == L1_STEP) ev = se[ring(z, NER) * NE + (y + H) * EX + (x + H)];
-      gst(eo, gidx(z, y0 + y, x0 + x), make_float2(ev.x + c0[k], ev.y + c1[k]));
+    for (int j = 0; j < PIN; ++j) {
+      const int i = threadIdx.x + j * NTH;
+      if (i < NB) dst[i] = vin[j];
     }
   };
 
-  if (VAR == L1_RESID) {
-    // t = r - W*e - a (.) (KA*e) on the tile, e planes z-1..z+1 (halo 1)
-    for (int k = zb - 1; k <= ze; ++k) {
-      load_e(k);
-      __syncthreads();
-      const int z = k - 1;
-      if (z >= zb) {
-        int eb[PO];
-        bool ok[PO];
-        float2 rv[PO], av[PO];
+  // ---- accumulators ---------------------------------------------------------
+  float tw0[3][RESID ? PO : PT], tw1[3][RESID ? PO : PT], tk0[3][RESID ? PO : PT],
+      tk1[3][RESID ? PO : PT];
+  float uc0[3][PU], uc1[3][PU];
+  float oc0[3][PO], oc1[3][PO];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int k = 0; k < (RESID ? PO : PT); ++k) tw0[q][k] = tw1[q][k] = tk0[q][k] = tk1[q][k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < PU; ++k) uc0[q][k] = uc1[q][k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < PO; ++k) oc0[q][k] = oc1[q][k] = 0.f;
+  }
+  // operands of the outputs finished next: r, a of the t plane, s of the u
+  // plane (loaded after their previous use, consumed one iteration later)
+  constexpr int PR = RESID ? PO : PT;
+  float2 rv[PR], av[PR], sv[PU];
+  auto load_ra = [&](int q) {
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+      int gy, gx;
+      bool in;
+      if constexpr (RESID) { gy = y0 + oy_[k]; gx = x0 + ox_[k]; in = threadIdx.x + k * NTH < NO; }
+      else { gy = y0 - 2 + ty_[k]; gx = x0 - 2 + tx_[k]; in = threadIdx.x + k * NTH < NT; }
+      const bool ok = in && inside(q, gy, gx);
+      rv[k] = ldz(r, gidx(q, gy, gx), ok);
+      av[k] = ldz(a, gidx(q, gy, gx), ok);
+    }
+  };
+  auto load_s = [&](int p) {
+#pragma unroll
+    for (int k = 0; k < PU; ++k) {
+      const int gy = y0 - 1 + uy_[k], gx = x0 - 1 + ux_[k];
+      const bool ok = threadIdx.x + k * NTH < NU && inside(p, gy, gx);
+      sv[k] = ldz(s, gidx(p, gy, gx), ok);
+    }
+  };
+
+  if constexpr (RESID) {
+    // plane k of e feeds t(k - 1), t(k), t(k + 1); t(k - 1) is written
+    const int k0 = zb - 1, k1 = ze;
+    load_in(k0);
+    store_in(k0);
+    load_ra(k0 - 1);
+    for (int k = k0; k <= k1; ++k) {
+      if (k + 1 <= k1) load_in(k + 1);
+      __syncthreads();                          // e(k) in LDS; e(k - 1)'s slot is free
+      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->W[0][0][0],
+              &wg->KA[0][0][0], tb, tw0, tw1, tk0, tk1, integral_constant<int, PO>());
+      const int q = k - 1;
+      if (q >= zb) {
 #pragma unroll
         for (int j = 0; j < PO; ++j) {
-          const int i = threadIdx.x + j * NTH;
-          const int y = i / TX, x = i % TX;
-          ok[j] = i < NO && inside(z, y0 + y, x0 + x);
-          rv[j] = ldz(r, gidx(z, y0 + y, x0 + x), ok[j]);
-          av[j] = ldz(a, gidx(z, y0 + y, x0 + x), ok[j]);
-          eb[j] = (i < NO) ? (y + 1) * EX + (x + 1) : EX + 1;
-        }
-        float w0[PO], w1[PO], k0[PO], k1[PO];
-#pragma unroll
-        for (int j = 0; j < PO; ++j) w0[j] = w1[j] = k0[j] = k1[j] = 0.f;
-        conv2pair(se, NER, NE, z, EX, &wg->W[0][0][0], &wg->KA[0][0][0], eb, w0, w1, k0, k1,
-                  std::integral_constant<int, PO>());
-#pragma unroll
-        for (int j = 0; j < PO; ++j) {
-          if (!ok[j]) continue;
-          const int i = threadIdx.x + j * NTH;
-          const int y = i / TX, x = i % TX;
-          gst(eo, gidx(z, y0 + y, x0 + x), make_float2(rv[j].x - w0[j] - av[j].x * k0[j],
-                                                       rv[j].y - w1[j] - av[j].y * k1[j]));
+          const int gy = y0 + oy_[j], gx = x0 + ox_[j];
+          if (threadIdx.x + j * NTH < NO && inside(q, gy, gx))
+            gst(eo, gidx(q, gy, gx), make_float2(rv[j].x - tw0[0][j] - av[j].x * tk0[0][j],
+                                                 rv[j].y - tw1[0][j] - av[j].y * tk1[0][j]));
         }
       }
-      __syncthreads();
+      shift(tw0); shift(tw1); shift(tk0); shift(tk1);
+      if (k + 1 <= k1) {
+        load_ra(k);
+        store_in(k + 1);                        // into the other slot of the pair
+      }
     }
     return;
   }
-  // STEP: at k, e plane k arrives, t plane k-1, u plane k-2, output plane k-3.
-  // FIRST: t plane k (= r), u plane k-1, output plane k-2.
-  constexpr int LAG = (VAR == L1_STEP) ? 1 : 0;
-  for (int k = zb - 2 - LAG; k <= ze + 1 + LAG; ++k) {
-    if (VAR == L1_STEP) {
-      load_e(k);
-      __syncthreads();
+
+  // STEP: plane k of e feeds t(k-1..k+1); t(k-1) feeds u(k-2..k); u(k-2)
+  // feeds out(k-3..k-1).  FIRST: plane k of r (= t) feeds u(k-1..k+1);
+  // u(k-1) feeds out(k-2..k).
+  constexpr int LAG = STEP ? 1 : 0;
+  const int k0 = zb - 2 - LAG, k1 = ze + 1 + LAG;
+  load_in(k0);
+  store_in(k0);
+  if constexpr (STEP) load_ra(k0 - 1);
+  load_s(k0 - 1 - LAG);
+  for (int k = k0; k <= k1; ++k) {
+    if (k + 1 <= k1) load_in(k + 1);
+    __syncthreads();                            // input plane k published; su, st free
+    if constexpr (STEP) {
+      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->W[0][0][0],
+              &wg->KA[0][0][0], tb, tw0, tw1, tk0, tk1, integral_constant<int, PT>());
+      // t(k - 1) = r - W e - a (.) (KA e), zero outside the grid
+      const int q = k - 1;
+#pragma unroll
+      for (int j = 0; j < PT; ++j) {
+        const int i = threadIdx.x + j * NTH;
+        if (i < NT)
+          st[i] = inside(q, y0 - 2 + ty_[j], x0 - 2 + tx_[j])
+                      ? make_float2(rv[j].x - tw0[0][j] - av[j].x * tk0[0][j],
+                                    rv[j].y - tw1[0][j] - av[j].y * tk1[0][j])
+                      : zero;
+      }
+      shift(tw0); shift(tw1); shift(tk0); shift(tk1);
+      if (k + 1 <= k1) load_ra(k);
+      __syncthreads();                          // t(k - 1) published
     }
-    const int q = k - LAG, p = q - 1, z = q - 2;
-    if (q >= zb - 2) make_t(q);
-    __syncthreads();
-    if (p >= zb - 1) make_u(p);
-    __syncthreads();
-    if (z >= zb) make_out(z);
-    __syncthreads();
+    // u(p) = s (.) (KS * t), p = k - 1 - LAG, zero outside the grid
+    {
+      scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], &wg->KS[0][0][0], ub,
+              uc0, uc1, uc0, uc1, integral_constant<int, PU>());
+      const int p = k - 1 - LAG;
+#pragma unroll
+      for (int j = 0; j < PU; ++j) {
+        const int i = threadIdx.x + j * NTH;
+        if (i < NU)
+          su[i] = inside(p, y0 - 1 + uy_[j], x0 - 1 + ux_[j])
+                      ? make_float2(sv[j].x * uc0[0][j], sv[j].y * uc1[0][j])
+                      : zero;
+      }
+      shift(uc0); shift(uc1);
+      if (k + 1 <= k1) load_s(p + 1);
+    }
+    __syncthreads();                            // u(p) published; st consumed
+    // out(z) = e + Wsm * u, z = k - 2 - LAG
+    {
+      scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], &wg->Wsm[0][0][0], ob,
+              oc0, oc1, oc0, oc1, integral_constant<int, PO>());
+      const int z = k - 2 - LAG;
+      if (z >= zb && z < ze) {
+#pragma unroll
+        for (int j = 0; j < PO; ++j) {
+          const int i = threadIdx.x + j * NTH;
+          const int gy = y0 + oy_[j], gx = x0 + ox_[j];
+          if (i < NO && inside(z, gy, gx)) {
+            float2 ev = zero;
+            if (STEP) ev = se[ring(z, NER) * NE + (oy_[j] + H) * EX + (ox_[j] + H)];
+            gst(eo, gidx(z, gy, gx), make_float2(ev.x + oc0[0][j], ev.y + oc1[0][j]));
+          }
+        }
+      }
+      shift(oc0); shift(oc1);
+      // the next input plane: its slot held e(k - 4) (STEP), read by the
+      // previous iteration's output phase; FIRST's r plane was last read by
+      // this iteration's u phase, finished at the barrier above
+      if (k + 1 <= k1) store_in(k + 1);
+    }
   }
 }
 
 template <int VAR>
-__global__ __launch_bounds__(NTH) void l1z_kernel(L1Args A) {
-  l1z_body<VAR>(A, A.wp, blockIdx.x);
+__global__ __launch_bounds__(NTH) void l1z_kernel(L1Args A, L1Weights w) {
+  l1z_body<VAR>(A, w, blockIdx.x);
 }
 
 template <int VAR>
@@ -499,7 +561,9 @@ __global__ __launch_bounds__(NTH) void l1z_kernel_batched(const L1Args* __restri
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
   const L1Args A = tab[batch_entry(row, np, p)];
-  l1z_body<VAR>(A, A.wp, blockIdx.x - pre[p]);
+  __shared__ L1Weights wsh;
+  stage_weights(A.wp, &wsh);
+  l1z_body<VAR>(A, wsh, blockIdx.x - pre[p]);
 }
 
 template <int D, int VAR>
@@ -531,10 +595,9 @@ hipError_t run(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
       hipLaunchKernelGGL((l1z_kernel_batched<VAR>), dim3(b->total), dim3(NTH), 0, s,
                          (const L1Args*)b->tab, b->pre, b->np, b->frozen, b->row);
     } else {
-      if (!l.wdev) return hipErrorInvalidValue;
       int nblk;
       const L1Args A = l1_args(l, l.wdev, &nblk);
-      hipLaunchKernelGGL((l1z_kernel<VAR>), dim3(nblk), dim3(NTH), 0, s, A);
+      hipLaunchKernelGGL((l1z_kernel<VAR>), dim3(nblk), dim3(NTH), 0, s, A, l.w);
     }
   } else {
     if (b) {

@@ -282,12 +282,27 @@ mcmg_status Ctx::plan_mfma() {
     mfma_pack_dims(dim, mode, cin, cout, bf, &op.cinp, &op.ncols, &op.npairs, &op.nsteps);
     op.on = false;
   };
-  // weight chunk: all K-steps at once when the LDS allows (one load latency
-  // per block), else halve until it fits
+  // weight chunk: all K-steps at once when the block fits 96 KB of LDS (one
+  // load latency per block, two blocks per CU), else halve (the chunks are
+  // then double-buffered) until it fits.  A chunk must keep the matrix
+  // cores busy for longer than a copy's latency (about 8k cycles of
+  // products per wave) for the double buffering to hide it; when the 96 KB
+  // budget (a large staged tile) leaves less, the chunk takes the whole LDS.
   auto kchunk_for = [&](const MOp& op, const Tile& t) {
+    auto bytes = [&](int kc) {
+      return mfma_lds_bytes(dim, bf, op.mode, t.mt, t.ntw, t.rpw, op.cinp, op.epi, kc, op.nsteps);
+    };
+    auto cycles = [&](int kc) {
+      return (double)kc * (op.epi == EPI_RESID ? 2 : 1) * t.rpw * t.mt * t.ntw * (bf ? 16.0 : 32.0);
+    };
     int kc = op.nsteps;
-    while (kc > 1 && mfma_lds_bytes(dim, bf, op.mode, t.mt, t.ntw, t.rpw, op.cinp, op.epi, kc) > 96 * 1024)
-      kc = (kc + 1) / 2;
+    if (!bf && dim == 3) return kc;   // 3D float32 streams its weights from global memory
+    while (kc > 1 && bytes(kc) > 96 * 1024) kc = (kc + 1) / 2;
+    if (bytes(kc) > 96 * 1024 || (kc < op.nsteps && cycles(kc) < 8192.0)) {
+      int big = op.nsteps;
+      while (big > 1 && bytes(big) > lds_max) big = (big + 1) / 2;
+      if (big > kc || bytes(kc) > 96 * 1024) kc = big;
+    }
     return kc;
   };
   // candidate tiles that fit, in a fixed preference order
@@ -300,7 +315,7 @@ mcmg_status Ctx::plan_mfma() {
           if (nt % ntw || !mfma_tile_ok(dim, op.epi, mt, ntw, rpw)) continue;
           const Tile t{mt, ntw, rpw};
           const int kc = kchunk_for(op, t);
-          if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cinp, op.epi, kc) > lds_max) continue;
+          if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cinp, op.epi, kc, op.nsteps) > lds_max) continue;
           c.push_back(t);
         }
     return c;
