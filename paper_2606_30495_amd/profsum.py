@@ -6,12 +6,17 @@
         [--kernel NAME=SOURCE ...] [--src NAME_PREFIX=SOURCE ...]
 
     python3 -m paper_2606_30495_amd.profsum mfma <dir> [prefix ...]
+    python3 -m paper_2606_30495_amd.profsum counters <dir> [prefix ...]
 
 `mfma` summarises a run with `--pmc MfmaUtil MfmaFlopsBF16` per kernel name
 (those starting with one of the prefixes, default mconv_kernel and
 mstep_kernel): dispatches, mean matrix-core flops per dispatch as counted
 by the hardware, mean dispatch duration, flops over duration, and
 MfmaUtil, the matrix-core busy cycles over the busy cycles of all SIMDs.
+
+`counters` prints, per kernel name (those starting with one of the
+prefixes, default all), the dispatch count and the mean per dispatch of
+every counter the run collected.
 
 `traffic` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
 name, scales each by the calibration copy kernel's bytes-moved / counter
@@ -121,6 +126,34 @@ def replay_run(trace, kernel):
             f"{sum(dur) / len(dur) / 1e3:.3f} us, mean start-to-start {span / len(best) / 1e3:.3f} us")
 
 
+def counters(d, prefixes):
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    names = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            k = short(r["Kernel_Name"])
+            if prefixes and not k.startswith(tuple(prefixes)):
+                continue
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            per.setdefault(k, {}).setdefault(c, {})
+            disp = r.get("Dispatch_Id", r.get("Correlation_Id", ""))
+            per[k][c][disp] = per[k][c].get(disp, 0.0) + float(r["Counter_Value"])
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---|" + "---|" * len(names)]
+    rows = []
+    for k, cs in per.items():
+        n = max(len(v) for v in cs.values())
+        means = [sum(cs[c].values()) / max(len(cs[c]), 1) if c in cs else float("nan") for c in names]
+        rows.append((k, n, means))
+    rows.sort(key=lambda t: -t[1])
+    for k, n, means in rows:
+        out.append(f"| `{k}` | {n} | " + " | ".join(f"{m:.4g}" for m in means) + " |")
+    return "\n".join(out)
+
+
 def mfma(d, prefixes):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     per = {}
@@ -156,6 +189,9 @@ def mfma(d, prefixes):
 def main(argv):
     if argv[0] == "mfma":
         print(mfma(argv[1], argv[2:] or ["mconv_kernel", "mstep_kernel"]))
+        return
+    if argv[0] == "counters":
+        print(counters(argv[1], argv[2:]))
         return
     if argv[0] == "replay":
         print(replay_run(argv[1], argv[2]))
