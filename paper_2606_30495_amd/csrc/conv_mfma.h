@@ -42,6 +42,11 @@ MArgs mfma_args(const MfmaConv& a, int* nblk);
 // device array of MArgs, b.pre the block prefix (np + 1 ints).
 hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b, hipStream_t s);
 
+// Zero K steps stored after every packed weight tensor: the 3D float32
+// kernels load B fragments in groups of four steps, up to three groups past
+// the last step they multiply, without a bounds clamp.
+constexpr int MFMA_PAD_STEPS = 16;
+
 // Padded sizes of the packed operands (see conv_mfma.hip for the layout).
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
                     int* npairs, int* nsteps);

@@ -136,22 +136,25 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   if constexpr (!BG) wfetch(0, ks0, bsm);
   constexpr int GS = 4;   // K steps per group of B loads (float32)
   float bq0[GS][NACC][NTW], bq1[GS][NACC][NTW];   // unused unless BG
+  // B fragment of step ss, tile t: row 4 ss + lg, column col0 + 16 t + li.
+  // The row base is uniform (a scalar address), the lane part a constant
+  // offset; steps past the end read the zero rows stored after the tensor
+  // and are never multiplied.
+  const int blane = lg * ncols + col0 + li;
   auto loadB = [&](int s0, float (&b)[GS][NACC][NTW]) {
-    const gptr<const float> wAf = (gptr<const float>)wA, wBf = (gptr<const float>)wB;
+    const gptr<const float> wAf = (gptr<const float>)wA + (size_t)4 * s0 * ncols;
+    const gptr<const float> wBf = (gptr<const float>)wB + (size_t)4 * s0 * ncols;
 #pragma unroll
-    for (int g = 0; g < GS; ++g) {
-      // steps past the end re-read the last one and are never multiplied
-      const int ss = (s0 + g) < nsteps ? (s0 + g) : nsteps - 1;
+    for (int g = 0; g < GS; ++g)
 #pragma unroll
       for (int aa = 0; aa < NACC; ++aa)
 #pragma unroll
         for (int t = 0; t < NTW; ++t)
-          b[g][aa][t] = (aa ? wBf : wAf)[(size_t)(4 * ss + lg) * ncols + col0 + t * 16 + li];
-    }
+          b[g][aa][t] = (aa ? wBf : wAf)[blane + (4 * g) * ncols + t * 16];
   };
   if constexpr (BG) {
     loadB(0, bq0);
-    if (GS < nsteps) loadB(GS, bq1);
+    loadB(GS, bq1);
   }
 
   // ---- stage the input tile: loads are issued in batches of SB per thread
@@ -307,17 +310,30 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     // two groups of products to land (the first two are issued before the
     // input tile is staged).  A fragments come from the staged tile, one
     // step ahead.  No barrier inside the K loop.
+    // float32 packs one input channel per K lane group and pads the
+    // channels to a multiple of 4, so the four pairs of a step are four
+    // consecutive channels of ONE tap: the tap and its staged offset are
+    // the same in every lane and advance as scalars (same pairs, same
+    // order as the pair walk).
+    int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0;
     auto loadA = [&](Frag (&af)[RPW][MT]) {
-      int tap, cb;
-      pw.take(tap, cb);
-      int dz = 0, dy, dx;
-      if (D == 2) { dy = tap / G::W; dx = tap % G::W; }
-      else { dz = tap / (G::W * G::W); dy = (tap / G::W) % G::W; dx = tap % G::W; }
-      const int aoff = ((dz * G::HY + dy) * G::HX + dx) * stride + cb * KV;
+      const int aoff = s_toff * stride + s_cb + lg;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int m = 0; m < MT; ++m) af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
+      s_cb += 4;
+      if (s_cb == cinp) {
+        s_cb = 0;
+        ++s_dx;
+        ++s_toff;
+        if (s_dx == G::W) {
+          s_dx = 0;
+          ++s_dy;
+          s_toff += G::HX - G::W;
+          if (s_dy == G::W) { s_dy = 0; s_toff += (G::HY - G::W) * G::HX; }
+        }
+      }
     };
     Frag a0[RPW][MT], a1[RPW][MT];
     loadA(a0);
@@ -327,23 +343,28 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
       for (int g = 0; g < GS; ++g) {
         const int ss = s0 + g;
         if (ss < nsteps) {
+          // the products are issued first, then the next step's fragments
+          // are requested: their LDS latency runs under the products, and
+          // the wait before the next products covers only them
           if ((g & 1) == 0) {
-            if (ss + 1 < nsteps) loadA(a1);
             mma(b[g], a0);
+            if (ss + 1 < nsteps) loadA(a1);
           } else {
-            if (ss + 1 < nsteps) loadA(a0);
             mma(b[g], a1);
+            if (ss + 1 < nsteps) loadA(a0);
           }
         }
       }
     };
+    // the look-ahead loads are unconditional (past the end they read the
+    // zero steps stored after the tensor): every path through the loop then
+    // has the same loads in flight, so the compiler's counter waits stay
+    // exact instead of assuming a skipped load
     for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
       group(s0, bq0);
-      if (s0 + 2 * GS < nsteps) loadB(s0 + 2 * GS, bq0);
-      if (s0 + GS < nsteps) {
-        group(s0 + GS, bq1);
-        if (s0 + 3 * GS < nsteps) loadB(s0 + 3 * GS, bq1);
-      }
+      loadB(s0 + 2 * GS, bq0);
+      if (s0 + GS < nsteps) group(s0 + GS, bq1);
+      loadB(s0 + 3 * GS, bq1);
     }
   } else {
     for (int s0 = 0, chunk = 0; s0 < nsteps; s0 += KS, ++chunk) {

@@ -156,6 +156,7 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
   constexpr int EY = C2Y + 2, EX = C2X + 2, NE = EY * EX;
   constexpr int PE = (NE + 255) / 256, NO = C2Y * C2X, PO = (NO + 255) / 256;
   __shared__ float2 se[3 * NE];
+  __shared__ float4 sw[27];                 // [tap] (w00, w01, w10, w11)
   const gptr<const TIN> __restrict__ x = to_global<const TIN>(A.x);
   const gptr<TOUT> __restrict__ y = to_global<TOUT>(A.y);
   const gptr<const float> __restrict__ w = to_global<const float>(A.w);
@@ -172,8 +173,14 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
     return xx >= 0 && xx < NX && yy >= 0 && yy < NY && z >= 0 && z < NZ;
   };
   auto gidx = [&](int z, int yy, int xx) { return ((long long)z * NY + yy) * NX + xx; };
-  for (int k = zb - 1; k <= ze; ++k) {
-    float2 v[PE];
+  // the 108 weights go to LDS once and are read there with uniform
+  // addresses (through the pointer they were vector loads)
+  if (threadIdx.x < 27)
+    sw[threadIdx.x] = make_float4(w[threadIdx.x * 4 + 0], w[threadIdx.x * 4 + 1],
+                                  w[threadIdx.x * 4 + 2], w[threadIdx.x * 4 + 3]);
+  // input plane k (halo 1), loaded one plane ahead of its store
+  float2 v[PE];
+  auto load_plane = [&](int k) {
 #pragma unroll
     for (int j = 0; j < PE; ++j) {
       const int i = threadIdx.x + j * 256;
@@ -184,12 +191,16 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
         v[j] = make_float2(load_as_f32(x, 2 * g), load_as_f32(x, 2 * g + 1));
       }
     }
+  };
+  load_plane(zb - 1);
+  for (int k = zb - 1; k <= ze; ++k) {
     float2* dst = se + ring3(k) * NE;
 #pragma unroll
     for (int j = 0; j < PE; ++j) {
       const int i = threadIdx.x + j * 256;
       if (i < NE) dst[i] = v[j];
     }
+    if (k + 1 <= ze) load_plane(k + 1);
     __syncthreads();
     const int z = k - 1;
     if (z >= zb) {
@@ -204,18 +215,17 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
 #pragma unroll 1
       for (int dz = 0; dz < 3; ++dz) {
         const float2* P = se + ring3(z - 1 + dz) * NE;
-        const gptr<const float> wz = w + dz * 9 * 4;                      // [tap][cin][cpad = 2]
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
           const int to = (t / 3) * EX + (t % 3);
-          const float w00 = wz[t * 4 + 0], w01 = wz[t * 4 + 1], w10 = wz[t * 4 + 2], w11 = wz[t * 4 + 3];
+          const float4 wt = sw[dz * 9 + t];
 #pragma unroll
           for (int j = 0; j < PO; ++j) {
             const float2 e = P[eb[j] + to];
-            a0[j] = fmaf(e.x, w00, a0[j]);
-            a1[j] = fmaf(e.x, w01, a1[j]);
-            a0[j] = fmaf(e.y, w10, a0[j]);
-            a1[j] = fmaf(e.y, w11, a1[j]);
+            a0[j] = fmaf(e.x, wt.x, a0[j]);
+            a1[j] = fmaf(e.x, wt.y, a1[j]);
+            a0[j] = fmaf(e.y, wt.z, a0[j]);
+            a1[j] = fmaf(e.y, wt.w, a1[j]);
           }
         }
       }

@@ -109,7 +109,7 @@ std::string tune_key(int dim, int bf16, const MOp& op) {
 std::vector<float> pack_gemm(const std::vector<float>& w, int dim, const MOp& op, int KV) {
   const int T3 = dim == 2 ? 9 : 27;
   const int cpv = op.cinp / KV;
-  std::vector<float> out((size_t)4 * op.nsteps * op.ncols * KV, 0.f);
+  std::vector<float> out((size_t)4 * (op.nsteps + MFMA_PAD_STEPS) * op.ncols * KV, 0.f);
   for (int q = 0; q < op.npairs; ++q) {
     const int tap = q / cpv, cb = q % cpv;
     for (int col = 0; col < op.ncols; ++col)
