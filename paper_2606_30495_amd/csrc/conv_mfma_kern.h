@@ -209,9 +209,10 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   __syncthreads();                                   // tile and first weight chunk published
 
   // output offsets and epilogue operands of every accumulator element; for
-  // small tiles the operands are fetched here, so their latency overlaps
-  // the K loop instead of following it
-  constexpr bool PREF = RPW * MT * NTW <= 2;
+  // small tiles, and in 3D float32 wherever they take at most 16 registers
+  // (more would cost a wave per SIMD), the operands are fetched here, so
+  // their latency overlaps the K loop instead of following it
+  constexpr bool PREF = RPW * MT * NTW <= 2 || (BG && RPW * MT * NTW * NACC <= 4);
   auto out_off = [&](int i, int m, int t, int rr) -> long long {
     const int rho = wave + 4 * i;
     const int gy = y0 + rho % G::TY, gz = z0 + rho / G::TY;

@@ -264,6 +264,16 @@ struct L1Weights {            // [cout][cin][tap] of the level-1 tensors
   float KS[2][2][27];
   float Wsm[2][2][27];
 };
+static_assert(sizeof(L1Weights) == 432 * sizeof(float), "W, KA, KS, Wsm packed in this order");
+// The same weights in the tap-major order of the 3D sweep: per in-plane tap
+// t (dy, dx row-major), per plane offset dz, the 2 x 2 channel block
+// (c00, c01, c10, c11) of W followed by that of KA; then KS and Wsm the
+// same way without a partner.
+struct L1ZWeights {
+  float WK[9][3][8];
+  float KS[9][3][4];
+  float Wsm[9][3][4];
+};
 enum { L1_STEP = 0, L1_FIRST = 1, L1_RESID = 2 };
 struct L1Launch {
   int dim, var;

@@ -245,6 +245,30 @@ __device__ __forceinline__ void stage_weights(const L1Weights* __restrict__ src,
   __syncthreads();
 }
 
+// Element i of the tap-major 3D layout (see L1ZWeights) as an index into
+// the [cout][cin][27 taps] layout of L1Weights.
+__host__ __device__ inline int l1z_source(int i) {
+  int tensor, t, dz, k;
+  if (i < 216) {                     // WK[t][dz][8]: W block, then KA block
+    t = i / 24; dz = (i / 8) % 3; k = i % 8;
+    tensor = k < 4 ? 0 : 1;
+    k &= 3;
+  } else {                           // KS, Wsm: [t][dz][4]
+    const int j = (i - 216) % 108;
+    tensor = 2 + (i - 216) / 108;
+    t = j / 12; dz = (j / 4) % 3; k = j % 4;
+  }
+  return tensor * 108 + k * 27 + dz * 9 + t;   // [cout][cin] = (k >> 1, k & 1)
+}
+
+__device__ __forceinline__ void stage_weights_z(const L1Weights* __restrict__ src, L1ZWeights* dst) {
+  constexpr int NW = sizeof(L1ZWeights) / sizeof(float);
+  const gptr<const float> s = to_global<const float>(src);
+  float* d = reinterpret_cast<float*>(dst);
+  for (int i = threadIdx.x; i < NW; i += NTH) d[i] = s[l1z_source(i)];
+  __syncthreads();
+}
+
 // Ring slot of plane `pl` (pl >= -4 R) in a ring of R planes.
 __device__ __forceinline__ int ring(int pl, int R) { return (pl + 4 * R) % R; }
 
@@ -259,7 +283,7 @@ __device__ __forceinline__ int ring(int pl, int R) { return (pl + 4 * R) % R; }
 // The weights come by value as a kernel argument (single problem: scalar
 // loads from the argument segment) or staged in LDS (batched launches).
 template <int VAR>
-__device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, const int vblk) {
+__device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, const int vblk) {
   constexpr int TY = G3::TY, TX = G3::TX, ZC = G3::ZC;
   constexpr bool STEP = VAR == L1_STEP, FIRST = VAR == L1_FIRST, RESID = VAR == L1_RESID;
   // e box (STEP: halo 3 around the tile; RESID: halo 1); FIRST has e = 0
@@ -283,7 +307,7 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
   const gptr<const float2> __restrict__ r = to_global<const float2>(A.r);
   const gptr<const float2> __restrict__ a = to_global<const float2>(A.a);
   const gptr<const float2> __restrict__ s = to_global<const float2>(A.s);
-  const L1Weights* wg = &wt;
+  const L1ZWeights* wg = &wt;
   const int NZ = A.n.n[0], NY = A.n.n[1], NX = A.n.n[2];
   const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
   const int per = (ntiles + 7) / 8;
@@ -300,12 +324,15 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
 
   // Scatter plane P (pitch = its box width) into the accumulators of the
   // outputs one behind (slot 0, dz = 2), level (slot 1, dz = 1) and one
-  // ahead (slot 2, dz = 0) of it; X holds the 2 x 2 channel block of one
-  // weight tensor, Y (when PAIR) a second one read from the same values.
-  auto scatter = [&](auto pair, const float2* P, int pitch, const float* Xw, const float* Yw,
-                     const int* base, auto& c0, auto& c1, auto& d0, auto& d1, auto npts) {
+  // ahead (slot 2, dz = 0) of it.  T holds the tap-major weights: per
+  // in-plane tap, per dz, the 2 x 2 channel block X (and, when PAIR, the
+  // block Y of a second tensor read from the same values right after it),
+  // so one tap's weights are one contiguous run.
+  auto scatter = [&](auto pair, const float2* P, int pitch, const float* T, const int* base,
+                     auto& c0, auto& c1, auto& d0, auto& d1, auto npts) {
     constexpr bool PAIR = decltype(pair)::value;
     constexpr int NP = decltype(npts)::value;
+    constexpr int TS = PAIR ? 24 : 12;   // floats per in-plane tap
     // taps at run time: only one tap's 12 (24) weights are live
 #pragma unroll 1
     for (int t = 0; t < 9; ++t) {
@@ -313,19 +340,19 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
       float2 v[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) v[k] = P[base[k] + to];
+      const float* wt = T + t * TS;
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz) {
         const int slot = 2 - dz;
-        const float* w = Xw + dz * 9;
-        const float a00 = w[t], a01 = w[27 + t], a10 = w[54 + t], a11 = w[81 + t];
+        const float* w = wt + dz * (TS / 3);
+        const float a00 = w[0], a01 = w[1], a10 = w[2], a11 = w[3];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
           c0[slot][k] = fmaf(a00, v[k].x, fmaf(a01, v[k].y, c0[slot][k]));
           c1[slot][k] = fmaf(a10, v[k].x, fmaf(a11, v[k].y, c1[slot][k]));
         }
         if constexpr (PAIR) {
-          const float* y = Yw + dz * 9;
-          const float b00 = y[t], b01 = y[27 + t], b10 = y[54 + t], b11 = y[81 + t];
+          const float b00 = w[4], b01 = w[5], b10 = w[6], b11 = w[7];
 #pragma unroll
           for (int k = 0; k < NP; ++k) {
             d0[slot][k] = fmaf(b00, v[k].x, fmaf(b01, v[k].y, d0[slot][k]));
@@ -454,8 +481,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
     for (int k = k0; k <= k1; ++k) {
       if (k + 1 <= k1) load_in(k + 1);
       __syncthreads();                          // e(k) in LDS; e(k - 1)'s slot is free
-      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->W[0][0][0],
-              &wg->KA[0][0][0], tb, tw0, tw1, tk0, tk1, integral_constant<int, PO>());
+      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
+              tw0, tw1, tk0, tk1, integral_constant<int, PO>());
       const int q = k - 1;
       if (q >= zb) {
 #pragma unroll
@@ -488,8 +515,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
     if (k + 1 <= k1) load_in(k + 1);
     __syncthreads();                            // input plane k published; su, st free
     if constexpr (STEP) {
-      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->W[0][0][0],
-              &wg->KA[0][0][0], tb, tw0, tw1, tk0, tk1, integral_constant<int, PT>());
+      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
+              tw0, tw1, tk0, tk1, integral_constant<int, PT>());
       // t(k - 1) = r - W e - a (.) (KA e), zero outside the grid
       const int q = k - 1;
 #pragma unroll
@@ -507,8 +534,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
     }
     // u(p) = s (.) (KS * t), p = k - 1 - LAG, zero outside the grid
     {
-      scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], &wg->KS[0][0][0], ub,
-              uc0, uc1, uc0, uc1, integral_constant<int, PU>());
+      scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0, uc1,
+              integral_constant<int, PU>());
       const int p = k - 1 - LAG;
 #pragma unroll
       for (int j = 0; j < PU; ++j) {
@@ -524,8 +551,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
     __syncthreads();                            // u(p) published; st consumed
     // out(z) = e + Wsm * u, z = k - 2 - LAG
     {
-      scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], &wg->Wsm[0][0][0], ob,
-              oc0, oc1, oc0, oc1, integral_constant<int, PO>());
+      scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0, oc1,
+              integral_constant<int, PO>());
       const int z = k - 2 - LAG;
       if (z >= zb && z < ze) {
 #pragma unroll
@@ -549,7 +576,7 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1Weights& wt, c
 }
 
 template <int VAR>
-__global__ __launch_bounds__(NTH) void l1z_kernel(L1Args A, L1Weights w) {
+__global__ __launch_bounds__(NTH) void l1z_kernel(L1Args A, L1ZWeights w) {
   l1z_body<VAR>(A, w, blockIdx.x);
 }
 
@@ -561,8 +588,8 @@ __global__ __launch_bounds__(NTH) void l1z_kernel_batched(const L1Args* __restri
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
   const L1Args A = tab[batch_entry(row, np, p)];
-  __shared__ L1Weights wsh;
-  stage_weights(A.wp, &wsh);
+  __shared__ L1ZWeights wsh;
+  stage_weights_z(A.wp, &wsh);
   l1z_body<VAR>(A, wsh, blockIdx.x - pre[p]);
 }
 
@@ -597,7 +624,11 @@ hipError_t run(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
     } else {
       int nblk;
       const L1Args A = l1_args(l, l.wdev, &nblk);
-      hipLaunchKernelGGL((l1z_kernel<VAR>), dim3(nblk), dim3(NTH), 0, s, A, l.w);
+      L1ZWeights wz;
+      const float* src = &l.w.W[0][0][0];
+      float* dst = &wz.WK[0][0][0];
+      for (int i = 0; i < (int)(sizeof(L1ZWeights) / sizeof(float)); ++i) dst[i] = src[l1z_source(i)];
+      hipLaunchKernelGGL((l1z_kernel<VAR>), dim3(nblk), dim3(NTH), 0, s, A, wz);
     }
   } else {
     if (b) {
