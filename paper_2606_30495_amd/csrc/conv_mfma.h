@@ -47,6 +47,15 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
 // the last step they multiply, without a bounds clamp.
 constexpr int MFMA_PAD_STEPS = 16;
 
+// 3D float32 weights are packed by groups of four K steps, so that a lane
+// reads the B values of a whole group as one 16-byte vector: pair q (K step
+// q / 4, lane group q % 4) and column col of the GEMM's B sit at this float
+// index (the steps are rounded up to a multiple of 4 before the padding).
+inline size_t mfma_bg_index(int q, int col, int ncols) {
+  const int s = q / 4, lg = q % 4;
+  return (((size_t)(s / 4) * 4 + lg) * ncols + col) * 4 + (s % 4);
+}
+
 // Padded sizes of the packed operands (see conv_mfma.hip for the layout).
 void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, int* ncols,
                     int* npairs, int* nsteps);

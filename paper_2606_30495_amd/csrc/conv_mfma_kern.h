@@ -136,21 +136,26 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   if constexpr (!BG) wfetch(0, ks0, bsm);
   constexpr int GS = 4;   // K steps per group of B loads (float32)
   float bq0[GS][NACC][NTW], bq1[GS][NACC][NTW];   // unused unless BG
-  // B fragment of step ss, tile t: row 4 ss + lg, column col0 + 16 t + li.
-  // The row base is uniform (a scalar address), the lane part a constant
-  // offset; steps past the end read the zero rows stored after the tensor
-  // and are never multiplied.
+  // B fragments of the group of four steps s0 .. s0 + 3 (s0 a multiple of
+  // 4), tile t: with the weights packed by step groups (mfma_bg_index) they
+  // are one 16-byte vector per lane and tensor, at vector (s0 + lg) ncols +
+  // col0 + 16 t + li.  Groups past the end read the zero steps stored after
+  // the tensor and are never multiplied.
   const int blane = lg * ncols + col0 + li;
   auto loadB = [&](int s0, float (&b)[GS][NACC][NTW]) {
-    const gptr<const float> wAf = (gptr<const float>)wA + (size_t)4 * s0 * ncols;
-    const gptr<const float> wBf = (gptr<const float>)wB + (size_t)4 * s0 * ncols;
+    static_assert(GS == 4, "one vector per lane holds a group");
+    const gptr<const float4> wAf = (gptr<const float4>)wA + (size_t)s0 * ncols;
+    const gptr<const float4> wBf = (gptr<const float4>)wB + (size_t)s0 * ncols;
 #pragma unroll
-    for (int g = 0; g < GS; ++g)
+    for (int aa = 0; aa < NACC; ++aa)
 #pragma unroll
-      for (int aa = 0; aa < NACC; ++aa)
-#pragma unroll
-        for (int t = 0; t < NTW; ++t)
-          b[g][aa][t] = (aa ? wBf : wAf)[blane + (4 * g) * ncols + t * 16];
+      for (int t = 0; t < NTW; ++t) {
+        const float4 v = gld(aa ? wBf : wAf, (long long)(blane + t * 16));
+        b[0][aa][t] = v.x;
+        b[1][aa][t] = v.y;
+        b[2][aa][t] = v.z;
+        b[3][aa][t] = v.w;
+      }
   };
   if constexpr (BG) {
     loadB(0, bq0);
@@ -425,7 +430,9 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   }
 
   // ---- epilogue: per (row, m) the operands of all its outputs are loaded
-  // first (unless prefetched), then combined and stored
+  // first (unless prefetched; in 3D float32 as unconditional loads with a
+  // clamped index, so that they are all in flight together), then combined
+  // and stored
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
 #pragma unroll
@@ -440,6 +447,13 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
           if constexpr (PREF) {
             e0[t][rr] = pe0[PREF ? i : 0][PREF ? m : 0][PREF ? t : 0][rr];
             e1[t][rr] = pe1[PREF ? i : 0][PREF ? m : 0][PREF ? t : 0][rr];
+          } else if constexpr (BG) {
+            const long long oc = o[t][rr] >= 0 ? o[t][rr] : 0;
+            e0[t][rr] = 0.f;
+            e1[t][rr] = 0.f;
+            if (EPI == EPI_ADD) e0[t][rr] = y[oc];
+            else if (EPI == EPI_MUL) e0[t][rr] = feat[oc];
+            else if (EPI == EPI_RESID) { e0[t][rr] = r[oc]; e1[t][rr] = feat[oc]; }
           } else {
             e0[t][rr] = 0.f;
             e1[t][rr] = 0.f;

@@ -109,7 +109,9 @@ std::string tune_key(int dim, int bf16, const MOp& op) {
 std::vector<float> pack_gemm(const std::vector<float>& w, int dim, const MOp& op, int KV) {
   const int T3 = dim == 2 ? 9 : 27;
   const int cpv = op.cinp / KV;
-  std::vector<float> out((size_t)4 * (op.nsteps + MFMA_PAD_STEPS) * op.ncols * KV, 0.f);
+  const bool grouped = dim == 3 && KV == 1;   // 3D float32: see mfma_bg_index
+  const int steps = grouped ? (op.nsteps + 3) / 4 * 4 : op.nsteps;
+  std::vector<float> out((size_t)4 * (steps + MFMA_PAD_STEPS) * op.ncols * KV, 0.f);
   for (int q = 0; q < op.npairs; ++q) {
     const int tap = q / cpv, cb = q % cpv;
     for (int col = 0; col < op.ncols; ++col)
@@ -139,7 +141,7 @@ std::vector<float> pack_gemm(const std::vector<float>& w, int dim, const MOp& op
           // P is [C_coarse = cin][C_fine = cout][3^D]
           val = w[((size_t)ci * op.cout + c) * T3 + t3];
         }
-        out[((size_t)q * op.ncols + col) * KV + v] = val;
+        out[grouped ? mfma_bg_index(q, col, op.ncols) : ((size_t)q * op.ncols + col) * KV + v] = val;
       }
   }
   return out;
