@@ -60,7 +60,7 @@ constexpr bool tile_ok() {
 // One block of the convolution: `vblk` is the block index inside this
 // problem's grid (the batched wrapper maps the launch's blocks onto problems).
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
-__device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
+__device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const int slice) {
   const gptr<const float> __restrict__ x = to_global<const float>(A.x);
   const gptr<const unsigned char> wA = to_global<const unsigned char>(A.wA);
   const gptr<const unsigned char> wB = to_global<const unsigned char>(A.wB);
@@ -87,7 +87,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   if (tl >= ntiles) return;
   const int tx = tl % tiles_x, ty = (tl / tiles_x) % tiles_y, tz = tl / (tiles_x * tiles_y);
   const int x0 = tx * G::TX, y0 = ty * G::TY, z0 = tz * G::TZ;
-  const int col0 = blockIdx.y * NTW * 16;
+  const int col0 = slice * NTW * 16;
   // grids: 2D (n[0] rows, n[1] x), 3D (n[0] z, n[1] y, n[2] x)
   const int IX = (D == 2) ? in.n[1] : in.n[2], IY = (D == 2) ? in.n[0] : in.n[1];
   const int IZ = (D == 2) ? 1 : in.n[0];
@@ -170,6 +170,47 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     const bool vec4 = (cin % 4) == 0;
     const int ng = cinp / 4;
     const int total = G::NODES * ng;
+    // 3D float32 with whole groups of 4 channels: the batch's loads are
+    // unconditional (an index outside the grid is clamped to 0 and the value
+    // replaced by zero), so all of them are in flight at once, and the
+    // (node, channel group) split takes a float reciprocal instead of an
+    // integer division (exact: idx < 2^15)
+    if (BG && vec4) {
+      const float inv_ng = 1.0f / (float)ng;
+      // element offset of the staged tile's origin (negative at the low
+      // boundary: only ever added to an in-grid offset)
+      const long long tile0 = (((long long)sz * IY + sy) * IX + sx) * cin;
+      auto split = [&](int idx, int& node, int& c) {
+        node = (int)(((float)idx + 0.5f) * inv_ng);
+        c = (idx - node * ng) * 4;
+      };
+      for (int base = threadIdx.x; base < total; base += 256 * SB) {
+        float4 t[SB];
+        bool ok[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          int node, c;
+          split(idx, node, c);
+          const int hz = node / (G::HX * G::HY), rem = node - hz * (G::HX * G::HY);
+          const int hy = rem / G::HX, hx = rem - hy * G::HX;
+          ok[k] = (idx < total) & ((unsigned)(sx + hx) < (unsigned)IX) & ((unsigned)(sy + hy) < (unsigned)IY) &
+                  ((unsigned)(sz + hz) < (unsigned)IZ);
+          const int rel = ((hz * IY + hy) * IX + hx) * cin + c;
+          t[k] = gld((gptr<const float4>)(x + (ok[k] ? tile0 + rel : 0)), 0);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int idx = base + k * 256;
+          if (idx >= total) continue;
+          int node, c;
+          split(idx, node, c);
+          const float4 v = ok[k] ? t[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+          float* sp = reinterpret_cast<float*>(smem) + (size_t)node * stride + c;
+          sp[0] = v.x; sp[1] = v.y; sp[2] = v.z; sp[3] = v.w;
+        }
+      }
+    } else
     for (int base = threadIdx.x; base < total; base += 256 * SB) {
       float4 v[SB];
 #pragma unroll
@@ -321,51 +362,48 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
     // consecutive channels of ONE tap: the tap and its staged offset are
     // the same in every lane and advance as scalars (same pairs, same
     // order as the pair walk).
-    int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0;
+    int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0, s_k = 0;
+    // fragments of the walker's step, then one step on; the walker stops at
+    // the last step, so the look-ahead reads past it stay inside the tile
     auto loadA = [&](Frag (&af)[RPW][MT]) {
       const int aoff = s_toff * stride + s_cb + lg;
 #pragma unroll
       for (int i = 0; i < RPW; ++i)
 #pragma unroll
         for (int m = 0; m < MT; ++m) af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
-      s_cb += 4;
-      if (s_cb == cinp) {
-        s_cb = 0;
-        ++s_dx;
-        ++s_toff;
-        if (s_dx == G::W) {
-          s_dx = 0;
-          ++s_dy;
-          s_toff += G::HX - G::W;
-          if (s_dy == G::W) { s_dy = 0; s_toff += (G::HY - G::W) * G::HX; }
-        }
-      }
-    };
-    Frag a0[RPW][MT], a1[RPW][MT];
-    loadA(a0);
-    // the products of one group (A fragments alternate a0 / a1: GS is even)
-    auto group = [&](int s0, const float (&b)[GS][NACC][NTW]) {
-#pragma unroll
-      for (int g = 0; g < GS; ++g) {
-        const int ss = s0 + g;
-        if (ss < nsteps) {
-          // the products are issued first, then the next step's fragments
-          // are requested: their LDS latency runs under the products, and
-          // the wait before the next products covers only them
-          if ((g & 1) == 0) {
-            mma(b[g], a0);
-            if (ss + 1 < nsteps) loadA(a1);
-          } else {
-            mma(b[g], a1);
-            if (ss + 1 < nsteps) loadA(a0);
+      if (++s_k < nsteps) {
+        s_cb += 4;
+        if (s_cb == cinp) {
+          s_cb = 0;
+          ++s_dx;
+          ++s_toff;
+          if (s_dx == G::W) {
+            s_dx = 0;
+            ++s_dy;
+            s_toff += G::HX - G::W;
+            if (s_dy == G::W) { s_dy = 0; s_toff += (G::HY - G::W) * G::HX; }
           }
         }
       }
     };
+    // A fragments two steps ahead in four register sets (set = step mod 4,
+    // a compile-time index inside a group): the fragments of step s + 2 are
+    // requested before the products of step s are issued, so two steps of
+    // products cover their LDS latency
+    Frag aset[GS][RPW][MT];
+    loadA(aset[0]);
+    loadA(aset[1]);
+    auto group = [&](int s0, const float (&b)[GS][NACC][NTW]) {
+#pragma unroll
+      for (int g = 0; g < GS; ++g) {
+        loadA(aset[(g + 2) % GS]);
+        if (s0 + g < nsteps) mma(b[g], aset[g]);
+      }
+    };
     // the look-ahead loads are unconditional (past the end they read the
-    // zero steps stored after the tensor): every path through the loop then
-    // has the same loads in flight, so the compiler's counter waits stay
-    // exact instead of assuming a skipped load
+    // zero steps stored after the tensor, or the tile's last step): every
+    // path through the loop then has the same loads in flight, so the
+    // compiler's counter waits stay exact instead of assuming a skipped load
     for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
       group(s0, bq0);
       loadB(s0 + 2 * GS, bq0);
@@ -479,9 +517,14 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk) {
   }
 }
 
+// One problem: the blocks of all column slices share one grid dimension,
+// slices interleaved in runs of 8 (block b of run q is tile 8 q + b % 8 of
+// slice (b / 8) % nslices), so the slices of a tile are dispatched together
+// and to the same XCD (b mod 8) instead of one whole slice after another.
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
-__global__ __launch_bounds__(256) void mconv_kernel(MArgs A) {
-  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, blockIdx.x);
+__global__ __launch_bounds__(256) void mconv_kernel(MArgs A, int nslices) {
+  const int run = blockIdx.x / (8 * nslices), rem = blockIdx.x % (8 * nslices);
+  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, run * 8 + rem % 8, rem / 8);
 }
 
 // Batched form: one launch for several problems; pre[p] is the first block of
@@ -494,7 +537,7 @@ __global__ __launch_bounds__(256) void mconv_kernel_batched(const MArgs* __restr
   const int p = batch_find(pre, np, blockIdx.x);
   if (frozen && frozen[p]) return;
   const MArgs A = tab[batch_entry(row, np, p)];
-  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, blockIdx.x - pre[p]);
+  mconv_body<D, BF, MODE, EPI, MT, NTW, RPW>(A, blockIdx.x - pre[p], blockIdx.y);
 }
 
 template <int D, bool BF, int MODE, int EPI, int MT, int NTW, int RPW>
@@ -511,8 +554,8 @@ hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
     } else {
       int nblk;
       const MArgs A = mfma_args(a, &nblk);
-      hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(nblk, nslices), dim3(256),
-                         lds, s, A);
+      hipLaunchKernelGGL((mconv_kernel<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(nblk * nslices), dim3(256),
+                         lds, s, A, nslices);
     }
     return hipGetLastError();
   }
