@@ -362,53 +362,102 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
     // consecutive channels of ONE tap: the tap and its staged offset are
     // the same in every lane and advance as scalars (same pairs, same
     // order as the pair walk).
-    int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0, s_k = 0;
-    // fragments of the walker's step, then one step on; the walker stops at
-    // the last step, so the look-ahead reads past it stay inside the tile
-    auto loadA = [&](Frag (&af)[RPW][MT]) {
-      const int aoff = s_toff * stride + s_cb + lg;
+    if (cinp % 16 == 0) {
+      // channels in whole groups of 16: the four steps of a group are four
+      // channel quads of ONE tap, so the walker advances once per group and
+      // the group's A fragments sit at fixed offsets (0, 4, 8, 12) from its
+      // base; a group's fragments are read one group ahead (two register
+      // sets).  nsteps is a multiple of 4 here.
+      int q_cb = 0, q_dx = 0, q_dy = 0, q_toff = 0, q_k = 0;
+      const int ngroups = nsteps / GS;
+      auto loadAq = [&](Frag (&af)[GS][RPW][MT]) {
+        const int aoff = q_toff * stride + q_cb + lg;
 #pragma unroll
-      for (int i = 0; i < RPW; ++i)
+        for (int g = 0; g < GS; ++g)
 #pragma unroll
-        for (int m = 0; m < MT; ++m) af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
-      if (++s_k < nsteps) {
-        s_cb += 4;
-        if (s_cb == cinp) {
-          s_cb = 0;
-          ++s_dx;
-          ++s_toff;
-          if (s_dx == G::W) {
-            s_dx = 0;
-            ++s_dy;
-            s_toff += G::HX - G::W;
-            if (s_dy == G::W) { s_dy = 0; s_toff += (G::HY - G::W) * G::HX; }
+          for (int i = 0; i < RPW; ++i)
+#pragma unroll
+            for (int m = 0; m < MT; ++m)
+              af[g][i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff + 4 * g];
+        // (stops at the last group, so the look-ahead stays inside the tile)
+        if (++q_k < ngroups) {
+          q_cb += 4 * GS;
+          if (q_cb == cinp) {
+            q_cb = 0;
+            ++q_dx;
+            ++q_toff;
+            if (q_dx == G::W) {
+              q_dx = 0;
+              ++q_dy;
+              q_toff += G::HX - G::W;
+              if (q_dy == G::W) { q_dy = 0; q_toff += (G::HY - G::W) * G::HX; }
+            }
           }
         }
-      }
-    };
-    // A fragments two steps ahead in four register sets (set = step mod 4,
-    // a compile-time index inside a group): the fragments of step s + 2 are
-    // requested before the products of step s are issued, so two steps of
-    // products cover their LDS latency
-    Frag aset[GS][RPW][MT];
-    loadA(aset[0]);
-    loadA(aset[1]);
-    auto group = [&](int s0, const float (&b)[GS][NACC][NTW]) {
+      };
+      Frag aq0[GS][RPW][MT], aq1[GS][RPW][MT];
+      loadAq(aq0);
+      for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
+        loadAq(aq1);
 #pragma unroll
-      for (int g = 0; g < GS; ++g) {
-        loadA(aset[(g + 2) % GS]);
-        if (s0 + g < nsteps) mma(b[g], aset[g]);
+        for (int g = 0; g < GS; ++g) mma(bq0[g], aq0[g]);
+        loadB(s0 + 2 * GS, bq0);
+        loadAq(aq0);
+        if (s0 + GS < nsteps) {
+#pragma unroll
+          for (int g = 0; g < GS; ++g) mma(bq1[g], aq1[g]);
+        }
+        loadB(s0 + 3 * GS, bq1);
       }
-    };
-    // the look-ahead loads are unconditional (past the end they read the
-    // zero steps stored after the tensor, or the tile's last step): every
-    // path through the loop then has the same loads in flight, so the
-    // compiler's counter waits stay exact instead of assuming a skipped load
-    for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
-      group(s0, bq0);
-      loadB(s0 + 2 * GS, bq0);
-      if (s0 + GS < nsteps) group(s0 + GS, bq1);
-      loadB(s0 + 3 * GS, bq1);
+    } else {
+      int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0, s_k = 0;
+      // fragments of the walker's step, then one step on; the walker stops at
+      // the last step, so the look-ahead reads past it stay inside the tile
+      auto loadA = [&](Frag (&af)[RPW][MT]) {
+        const int aoff = s_toff * stride + s_cb + lg;
+  #pragma unroll
+        for (int i = 0; i < RPW; ++i)
+  #pragma unroll
+          for (int m = 0; m < MT; ++m) af[i][m] = reinterpret_cast<const float*>(smem)[abase[i][m] + aoff];
+        if (++s_k < nsteps) {
+          s_cb += 4;
+          if (s_cb == cinp) {
+            s_cb = 0;
+            ++s_dx;
+            ++s_toff;
+            if (s_dx == G::W) {
+              s_dx = 0;
+              ++s_dy;
+              s_toff += G::HX - G::W;
+              if (s_dy == G::W) { s_dy = 0; s_toff += (G::HY - G::W) * G::HX; }
+            }
+          }
+        }
+      };
+      // A fragments two steps ahead in four register sets (set = step mod 4,
+      // a compile-time index inside a group): the fragments of step s + 2 are
+      // requested before the products of step s are issued, so two steps of
+      // products cover their LDS latency
+      Frag aset[GS][RPW][MT];
+      loadA(aset[0]);
+      loadA(aset[1]);
+      auto group = [&](int s0, const float (&b)[GS][NACC][NTW]) {
+  #pragma unroll
+        for (int g = 0; g < GS; ++g) {
+          loadA(aset[(g + 2) % GS]);
+          if (s0 + g < nsteps) mma(b[g], aset[g]);
+        }
+      };
+      // the look-ahead loads are unconditional (past the end they read the
+      // zero steps stored after the tensor, or the tile's last step): every
+      // path through the loop then has the same loads in flight, so the
+      // compiler's counter waits stay exact instead of assuming a skipped load
+      for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
+        group(s0, bq0);
+        loadB(s0 + 2 * GS, bq0);
+        if (s0 + GS < nsteps) group(s0 + GS, bq1);
+        loadB(s0 + 3 * GS, bq1);
+      }
     }
   } else {
     for (int s0 = 0, chunk = 0; s0 < nsteps; s0 += KS, ++chunk) {
