@@ -8,7 +8,8 @@
     python3 -m paper_2606_30495_amd.profsum mfma <dir> [prefix ...]
     python3 -m paper_2606_30495_amd.profsum counters <dir> [prefix ...]
 
-`mfma` summarises a run with `--pmc MfmaUtil MfmaFlopsBF16` per kernel name
+`mfma` summarises a run with `--pmc MfmaUtil MfmaFlopsBF16` (or
+SQ_INSTS_VALU_MFMA_MOPS_F32, counted in units of 512 flops) per kernel name
 (those starting with one of the prefixes, default mconv_kernel and
 mstep_kernel): dispatches, mean matrix-core flops per dispatch as counted
 by the hardware, mean dispatch duration, flops over duration, and
@@ -154,6 +155,16 @@ def counters(d, prefixes):
     return "\n".join(out)
 
 
+# matrix-core flops per dispatch: a derived metric, or the MOPS counter (in
+# units of 512 flops)
+FLOP_COUNTERS = {"MfmaFlopsBF16": 1.0, "MfmaFlopsF32": 1.0,
+                 "SQ_INSTS_VALU_MFMA_MOPS_BF16": 512.0, "SQ_INSTS_VALU_MFMA_MOPS_F32": 512.0}
+
+
+def hw_flops(v):
+    return sum(v[c] * f for c, f in FLOP_COUNTERS.items() if c in v)
+
+
 def mfma(d, prefixes):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     per = {}
@@ -170,10 +181,10 @@ def mfma(d, prefixes):
     tot_fl = tot_ns = 0.0
     rows = []
     for k, e in per.items():
-        ds = [v for v in e.values() if "MfmaUtil" in v and "MfmaFlopsBF16" in v]
+        ds = [v for v in e.values() if "MfmaUtil" in v and any(c in v for c in FLOP_COUNTERS)]
         if not ds:
             continue
-        fl = sum(v["MfmaFlopsBF16"] for v in ds)
+        fl = sum(hw_flops(v) for v in ds)
         ns = sum(v["dur"] for v in ds)
         util = sum(v["MfmaUtil"] for v in ds) / len(ds)
         tot_fl += fl
@@ -181,7 +192,7 @@ def mfma(d, prefixes):
         rows.append((ns, f"| `{k}` | {len(ds)} | {fl / len(ds):.4g} | {ns / len(ds) / 1e3:.2f} | "
                          f"{fl / max(ns, 1) / 1e3:.1f} | {util:.2f} |"))
     out += [r for _, r in sorted(rows, reverse=True)]
-    out.append(f"\nall listed kernels: {tot_fl / max(tot_ns, 1) / 1e3:.1f} TFLOP/s of BF16 matrix-core work "
+    out.append(f"\nall listed kernels: {tot_fl / max(tot_ns, 1) / 1e3:.1f} TFLOP/s of matrix-core work "
                f"over their summed durations")
     return "\n".join(out)
 
