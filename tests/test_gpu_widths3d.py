@@ -5,9 +5,11 @@ PML = 48^3 extended, levels 48, 24, 12, 6, 3.
 
 Each tile shape that the 216^3 plan picks for some convolution is forced
 through MCMG_FORCE_TILE (where it is a candidate), so the wide-channel
-matrix-core paths of that plan run here: weights streamed through LDS in
-several chunks (at C = 48 and C = 96 the packed weights exceed the 96 KB
-chunk budget in both precisions), two and four column tiles per block, four
+matrix-core paths of that plan run here: in BF16 the weights stream through
+LDS in several chunks (at C = 48 and C = 96 the packed weights exceed the
+96 KB chunk budget); in FP32 they are read from global memory by runs of
+four K steps, and at C = 48 and C = 96 (channels in multiples of 16) the K
+walker advances once per group; two and four column tiles per block, four
 node rows per wave, and the prolongation from C = 96 to C = 48 as a
 384-column depth-to-space GEMM.  Bars: one application within 1e-5
 relative L2 (FP32) and 2e-2 (BF16); three FGMRES(20) iterations follow the
