@@ -33,6 +33,7 @@ struct MArgs {
   int cin, cinp, cout, ncols, nsteps, npairs;
   Dims in, out;
   int tiles_x, tiles_y, tiles_z, kchunk;
+  int zc;                // z-marching form: output planes per block
 };
 
 // Arguments and block count of one problem's launch.
@@ -66,6 +67,14 @@ size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int
 // Whether a tile (mt, ntw, rpw) is instantiated for this dim / epilogue.
 bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw);
 hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s);
+
+// z-marching form of the 3D float32 stride-1 convolution with 12 input
+// channels (conv_mfmaz.hip), selected as the tile (mt, ntw, rpw) = (1, 1,
+// MFMAZ_RPW): whether an operation can take it, its LDS bytes, its launch.
+constexpr int MFMAZ_RPW = 8;
+bool mfmaz_ok(int dim, int bf16, int mode, int cin, int cout);
+size_t mfmaz_lds_bytes(int epi);
+hipError_t launch_conv_mfmaz(const MfmaConv& a, const BatchLaunch* b, hipStream_t s);
 const char* mfma_kernel_name(const MfmaConv& a);
 
 }  // namespace mcmg

@@ -53,6 +53,7 @@ hipError_t mconv_3f_st(const MfmaConv& a, const BatchLaunch* b, hipStream_t s);
 namespace {
 
 hipError_t dispatch(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
+  if (a.rpw == MFMAZ_RPW) return launch_conv_mfmaz(a, b, s);
   const bool st = a.mode != CONV_S1;
   if (a.dim == 2) {
     if (a.bf16) return st ? mconv_2b_st(a, b, s) : mconv_2b_s1(a, b, s);
@@ -78,8 +79,41 @@ bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw) {
   return (epi == EPI_RESID ? 2 : 1) * rpw * mt * ntw <= 16 && rpw <= (dim == 2 ? 2 : 4);
 }
 
+// compute units of the current device (for sizing the z-marching form's chunks)
+static int device_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
 MArgs mfma_args(const MfmaConv& a, int* nblk) {
   int TX, TY, TZ;
+  if (a.rpw == MFMAZ_RPW) {
+    // z-marching form: 16 x 8 columns; the z range is cut into as many
+    // chunks as keep one wave of resident blocks busy
+    MArgs A;
+    A.x = a.x; A.wA = a.wA; A.wB = a.wB; A.y = a.y; A.r = a.r; A.feat = a.feat;
+    A.cin = a.cin; A.cinp = a.cinp; A.cout = a.cout; A.ncols = a.ncols; A.nsteps = a.nsteps;
+    A.npairs = a.npairs; A.in = a.in; A.out = a.out; A.kchunk = a.kchunk;
+    A.tiles_x = (a.out.n[2] + 15) / 16;
+    A.tiles_y = (a.out.n[1] + 7) / 8;
+    const int per_cu = (int)(160 * 1024 / mfmaz_lds_bytes(a.epi));
+    const int target = (per_cu > 0 ? per_cu : 1) * device_cus();
+    const int txy = A.tiles_x * A.tiles_y;
+    const int chunks = target / txy > 1 ? target / txy : 1;
+    A.zc = (a.out.n[0] + chunks - 1) / chunks;
+    A.tiles_z = (a.out.n[0] + A.zc - 1) / A.zc;
+    const int ntiles = A.tiles_x * A.tiles_y * A.tiles_z;
+    *nblk = ((ntiles + 7) / 8) * 8;
+    return A;
+  }
   mfma_tile(a.dim, a.mt, a.rpw, &TX, &TY, &TZ);
   // output tiles are taken over the GEMM row grid: S1 = output grid,
   // S2 = coarse output grid, T2 = coarse (input) grid
@@ -89,7 +123,7 @@ MArgs mfma_args(const MfmaConv& a, int* nblk) {
   MArgs A;
   A.x = a.x; A.wA = a.wA; A.wB = a.wB; A.y = a.y; A.r = a.r; A.feat = a.feat;
   A.cin = a.cin; A.cinp = a.cinp; A.cout = a.cout; A.ncols = a.ncols; A.nsteps = a.nsteps;
-  A.npairs = a.npairs; A.in = a.in; A.out = a.out; A.kchunk = a.kchunk;
+  A.npairs = a.npairs; A.in = a.in; A.out = a.out; A.kchunk = a.kchunk; A.zc = 0;
   A.tiles_x = (RX + TX - 1) / TX;
   A.tiles_y = (RY + TY - 1) / TY;
   A.tiles_z = (RZ + TZ - 1) / TZ;
@@ -105,6 +139,7 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
 
 size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
                       int kchunk, int nsteps) {
+  if (rpw == MFMAZ_RPW) return mfmaz_lds_bytes(epi);
   int TX, TY, TZ;
   mfma_tile(dim, mt, rpw, &TX, &TY, &TZ);
   auto ext = [&](int t) { return mode == CONV_S1 ? t + 2 : (mode == CONV_S2 ? 2 * t + 1 : t + 1); };
@@ -137,6 +172,7 @@ hipError_t launch_conv_mfma(const MfmaConv& a, hipStream_t s) {
 
 const char* mfma_kernel_name(const MfmaConv& a) {
   // the demangled template form profilers print
+  if (a.rpw == MFMAZ_RPW) return intern_name(std::string("mconvz_kernel<") + std::to_string(a.epi) + ">");
   return intern_name(std::string("mconv_kernel<") + std::to_string(a.dim) + ", " +
                      (a.bf16 ? "true" : "false") + ", " + std::to_string(a.mode) + ", " +
                      std::to_string(a.epi) + ", " + std::to_string(a.mt) + ", " +

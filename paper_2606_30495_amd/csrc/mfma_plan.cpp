@@ -320,6 +320,8 @@ mcmg_status Ctx::plan_mfma() {
           if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cinp, op.epi, kc, op.nsteps) > lds_max) continue;
           c.push_back(t);
         }
+    // the z-marching form (3D float32 stride-1, 12 input channels)
+    if (mfmaz_ok(dim, bf, op.mode, op.cin, op.cout) && op.ncols == 16) c.push_back(Tile{1, 1, MFMAZ_RPW});
     return c;
   };
   auto set_tile = [&](MOp& op, const Tile& t) {

@@ -26,6 +26,8 @@ pytestmark = pytest.mark.gpu
 DIM, N, NPML, CH = 3, 40, 4, (2, 12, 24, 48, 96)
 # every (mt, ntw, rpw) the packaged 216^3 plan holds, FP32 and BF16
 PLAN_TILES = ["1,1,4", "1,2,2", "1,1,1", "1,2,1", "2,2,1", "1,4,1", "2,2,2", "1,1,2", "1,4,2"]
+# the z-marching form of the C = 12 stride-1 convolutions (FP32), a tile of its own
+ZMARCH_TILE = "1,1,8"
 
 _cache = {}
 
@@ -60,7 +62,7 @@ def _apply(H, r):
     H.apply(to_dev(r), z)
     names = {rec["name"] for rec in H.prof_report()}
     H.prof_enable(False)
-    return to_host(z), sorted(n for n in names if n.startswith("mconv_kernel"))
+    return to_host(z), sorted(n for n in names if n.startswith(("mconv_kernel", "mconvz_kernel")))
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
@@ -79,7 +81,7 @@ def test_apply_default_plan(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
-@pytest.mark.parametrize("tile", PLAN_TILES)
+@pytest.mark.parametrize("tile", PLAN_TILES + [ZMARCH_TILE])
 def test_apply_forced_plan_tiles(tile, precision, monkeypatch):
     """The forced tile really runs (it names launched kernels), the result is
     within the bar, and it equals the default plan's bitwise: every tile
@@ -92,7 +94,13 @@ def test_apply_forced_plan_tiles(tile, precision, monkeypatch):
     H.close()
     err = rel_l2(z, d["z"])
     mt, ntw, rpw = tile.split(",")
-    forced = [k for k in kernels if k.endswith(f", {mt}, {ntw}, {rpw}>")]
+    if tile == ZMARCH_TILE:
+        forced = [k for k in kernels if k.startswith("mconvz_kernel<")]
+        if precision == "bf16":          # FP32 only: nothing to force
+            assert not forced, kernels
+            return
+    else:
+        forced = [k for k in kernels if k.endswith(f", {mt}, {ntw}, {rpw}>")]
     say(f"  rel L2 {err:.3e}; {len(forced)} of {len(kernels)} convolution kernels on the tile")
     assert forced, kernels
     assert err <= (1e-5 if precision == "fp32" else 2e-2), err
