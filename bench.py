@@ -77,6 +77,11 @@ def parse():
     return a
 
 
+# kernel-name prefixes of the matrix-core launches: implicit-GEMM
+# convolutions (tiled and z-marching forms) and fused smoothing steps
+MATRIX_CORE_KERNELS = ("mconv_kernel", "mconvz_kernel", "mstep_kernel")
+
+
 def roofline_for(rec, precision):
     """Roofline entry for one kernel record {avg_ms, flops_per_launch,
     bytes_per_launch}: the bound is the one its algorithmic intensity sits
@@ -85,7 +90,7 @@ def roofline_for(rec, precision):
     name = rec["name"]
     if name.startswith(("mconv_kernel<", "mstep_kernel<")) and ", true," in name:
         peak_fl, unit_bound = PEAK_BF16_TFLOPS, "mfma"
-    elif name.startswith(("mconv_kernel", "mstep_kernel")):
+    elif name.startswith(MATRIX_CORE_KERNELS):     # (the z-marching form is float32)
         peak_fl, unit_bound = PEAK_FP32_MFMA_TFLOPS, "mfma"
     elif name.startswith(("multidot", "update", "zupdate", "helm")):
         peak_fl, unit_bound = PEAK_FP64_TFLOPS, "alu"
@@ -107,14 +112,14 @@ def mfma_for(recs, precision, ms_per_step, iters):
     flops (2 per MAC) of every matrix-core launch of the profiled solve
     (implicit-GEMM convolutions and fused steps) over their summed
     event-timed durations, against the dense peak of the operand type."""
-    mm = [r for r in recs if r["name"].startswith(("mconv_kernel", "mstep_kernel"))]
+    mm = [r for r in recs if r["name"].startswith(MATRIX_CORE_KERNELS)]
     fl = sum(r["flops_per_launch"] * r["launches"] for r in mm)
     ms = sum(r["total_ms"] for r in mm)
     if not mm or ms <= 0:
         return None
     peak = PEAK_BF16_TFLOPS if precision == "bf16" else PEAK_FP32_MFMA_TFLOPS
     ach = fl / (ms * 1e-3) / 1e12
-    return {"kernels": "matrix-core convolutions (mconv_kernel, mstep_kernel)",
+    return {"kernels": "matrix-core convolutions (mconv_kernel, mconvz_kernel, mstep_kernel)",
             "achieved": round(ach, 3), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
             "ms_per_step": round(ms / max(iters, 1), 4),
             "share_of_step": round(ms / max(iters, 1) / ms_per_step, 3)}

@@ -10,7 +10,7 @@
 
 `mfma` summarises a run with `--pmc MfmaUtil MfmaFlopsBF16` (or
 SQ_INSTS_VALU_MFMA_MOPS_F32, counted in units of 512 flops) per kernel name
-(those starting with one of the prefixes, default mconv_kernel and
+(those starting with one of the prefixes, default mconv_kernel, mconvz_kernel and
 mstep_kernel): dispatches, mean matrix-core flops per dispatch as counted
 by the hardware, mean dispatch duration, flops over duration, and
 MfmaUtil, the matrix-core busy cycles over the busy cycles of all SIMDs.
@@ -199,7 +199,7 @@ def mfma(d, prefixes):
 
 def main(argv):
     if argv[0] == "mfma":
-        print(mfma(argv[1], argv[2:] or ["mconv_kernel", "mstep_kernel"]))
+        print(mfma(argv[1], argv[2:] or ["mconv_kernel", "mconvz_kernel", "mstep_kernel"]))
         return
     if argv[0] == "counters":
         print(counters(argv[1], argv[2:]))
