@@ -210,6 +210,35 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
           sp[0] = v.x; sp[1] = v.y; sp[2] = v.z; sp[3] = v.w;
         }
       }
+    } else if (BG && cin == 2) {
+      // the C = 2 finest level (channels padded to 4, one group per node):
+      // one unconditional 8-byte load per node, zero-selected, stored with
+      // the two padding channels
+      const long long tile0 = (((long long)sz * IY + sy) * IX + sx) * 2;
+      for (int base = threadIdx.x; base < total; base += 256 * SB) {
+        float2 t[SB];
+        bool ok[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int node = base + k * 256;
+          const int hz = node / (G::HX * G::HY), rem = node - hz * (G::HX * G::HY);
+          const int hy = rem / G::HX, hx = rem - hy * G::HX;
+          ok[k] = (node < total) & ((unsigned)(sx + hx) < (unsigned)IX) & ((unsigned)(sy + hy) < (unsigned)IY) &
+                  ((unsigned)(sz + hz) < (unsigned)IZ);
+          const int rel = ((hz * IY + hy) * IX + hx) * 2;
+          t[k] = gld((gptr<const float2>)(x + (ok[k] ? tile0 + rel : 0)), 0);
+        }
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+          const int node = base + k * 256;
+          if (node >= total) continue;
+          float* sp = reinterpret_cast<float*>(smem) + (size_t)node * stride;
+          sp[0] = ok[k] ? t[k].x : 0.f;
+          sp[1] = ok[k] ? t[k].y : 0.f;
+          sp[2] = 0.f;
+          sp[3] = 0.f;
+        }
+      }
     } else
     for (int base = threadIdx.x; base < total; base += 256 * SB) {
       float4 v[SB];

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void conv_direct_batched(const DArgs* __restri
 // once per block instead of once per tap.  Each output sums the same products
 // in the same order as conv_body (taps dz-major, then input channel; zero
 // outside the grid).
-constexpr int C2Y = 8, C2X = 64, C2Z = 32;
+constexpr int C2Y = 8, C2X = 64, C2Z = 8;
 
 __device__ __forceinline__ int ring3(int pl) { return (pl + 12) % 3; }
 
@@ -180,16 +180,17 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
                                   w[threadIdx.x * 4 + 2], w[threadIdx.x * 4 + 3]);
   // input plane k (halo 1), loaded one plane ahead of its store
   float2 v[PE];
+  // (unconditional loads from a clamped index, zero selected afterwards, so
+  // all of a plane's loads are in flight together)
   auto load_plane = [&](int k) {
 #pragma unroll
     for (int j = 0; j < PE; ++j) {
       const int i = threadIdx.x + j * 256;
       const int yy = y0 - 1 + i / EX, xx = x0 - 1 + i % EX;
-      v[j] = make_float2(0.f, 0.f);
-      if (i < NE && inside(k, yy, xx)) {
-        const long long g = gidx(k, yy, xx);
-        v[j] = make_float2(load_as_f32(x, 2 * g), load_as_f32(x, 2 * g + 1));
-      }
+      const bool ok = i < NE && inside(k, yy, xx);
+      const long long g = ok ? gidx(k, yy, xx) : 0;
+      const float v0 = load_as_f32(x, 2 * g), v1 = load_as_f32(x, 2 * g + 1);
+      v[j] = ok ? make_float2(v0, v1) : make_float2(0.f, 0.f);
     }
   };
   load_plane(zb - 1);
