@@ -249,25 +249,35 @@ __global__ __launch_bounds__(MC) void helm_march_kernel(HArgs A, int ntiles) {
   cplx nb[4];
   nbrs(z0, nb);
   double kk = k2[(long long)z0 * plane + col];
+  // the z coefficients of the plane (requested with the plane's other
+  // operands, one plane ahead)
+  const gptr<const double> g0 = sp ? to_global<const double>(A.op.g[0]) : k2;
+  cplx mz = ldv(A.op.cm[0], z0), pz = ldv(A.op.cp[0], z0);
+  double gz = g0[sp ? z0 : 0];
   for (int z = z0; z < ze; ++z) {
-    // next plane's operands, in flight while this plane is computed
-    cplx ucp2 = zero, nb2[4] = {zero, zero, zero, zero};
-    double kk2 = 0.0;
-    if (z + 1 < ze) {
-      if (z + 2 < NZ) ucp2 = ldv(u, (long long)(z + 2) * plane + col);
-      nbrs(z + 1, nb2);
-      kk2 = k2[(long long)(z + 1) * plane + col];
-    }
+    // next plane's operands, in flight while this plane is computed: the
+    // loads are unconditional (plane indices clamped, the last step re-reads
+    // its own plane, u beyond the grid replaced by zero afterwards), so no
+    // branch makes the compiler wait for them before the products
+    const int zn = z + 1 < ze ? z + 1 : z;
+    const int z2 = z + 2 < NZ ? z + 2 : NZ - 1;
+    cplx ucp2 = ldv(u, (long long)z2 * plane + col);
+    if (z + 2 >= NZ) ucp2 = zero;
+    cplx nb2[4];
+    nbrs(zn, nb2);
+    const double kk2 = k2[(long long)zn * plane + col];
+    const cplx mz2 = ldv(A.op.cm[0], zn), pz2 = ldv(A.op.cp[0], zn);
+    const double gz2 = g0[sp ? zn : 0];
     cplx m[3], pc[3], um[3], up[3];
-    m[0] = ldv(A.op.cm[0], z);
-    pc[0] = ldv(A.op.cp[0], z);
+    m[0] = mz;
+    pc[0] = pz;
     m[1] = m1; pc[1] = p1; m[2] = m2; pc[2] = p2;
     um[0] = ucm; up[0] = ucp;
     um[1] = nb[0]; up[1] = nb[1];
     um[2] = nb[2]; up[2] = nb[3];
     double gs = 0.0;
     if (sp) {
-      gs += to_global<const double>(A.op.g[0])[z];
+      gs += gz;
       gs += g1;
       gs += g2;
     }
@@ -276,6 +286,7 @@ __global__ __launch_bounds__(MC) void helm_march_kernel(HArgs A, int ntiles) {
     ucm = uc; uc = ucp; ucp = ucp2;
     nb[0] = nb2[0]; nb[1] = nb2[1]; nb[2] = nb2[2]; nb[3] = nb2[3];
     kk = kk2;
+    mz = mz2; pz = pz2; gz = gz2;
   }
 }
 
