@@ -79,8 +79,8 @@ bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw) {
   return (epi == EPI_RESID ? 2 : 1) * rpw * mt * ntw <= 16 && rpw <= (dim == 2 ? 2 : 4);
 }
 
-// compute units of the current device (for sizing the z-marching form's chunks)
-static int device_cus() {
+// compute units of the current device (for sizing the z-marching forms' chunks)
+int device_cus() {
   static int n = 0;
   if (n == 0) {
     int dev = 0, v = 0;

@@ -201,7 +201,7 @@ mcmg_status Engine::build() {
         for (int i = 0; i < np; ++i) {
           int nblk;
           const RecOp& o = works_[i]->ops[r][q];
-          tab[(size_t)r * np + i] = l1_args(o.l1, o.l1w_dev, &nblk);
+          tab[(size_t)r * np + i] = l1_args(o.l1, o.l1w_dev, &nblk, np);
           if (r == 0) pre[i + 1] = pre[i] + nblk;
         }
       ot.tab_off = b.add(tab);

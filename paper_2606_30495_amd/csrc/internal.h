@@ -144,6 +144,8 @@ void conv_work(const ConvLaunch& a, double* flops, double* bytes);
 
 // Fixed output-channel chunk per thread of the VALU direct convolution.
 int conv_chunk(int cout);
+// compute units of the current device (queried once; 256 if the query fails)
+int device_cus();
 hipError_t launch_conv(const ConvLaunch& a, hipStream_t s);
 
 // Fill n floats with zero (graph-safe, no memset node).
@@ -331,8 +333,11 @@ struct L1Args {
   const L1Weights* wp;
   Dims n;
   int tiles_x, tiles_y, tiles_z;
+  int zc;                // 3D: planes per block (the z chunk)
 };
-L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk);
+// nprob: problems sharing the launch (batched), which share the chip's
+// resident blocks when the 3D z chunk is sized
+L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk, int nprob = 1);
 hipError_t launch_level1_batched(int dim, int var, const BatchLaunch& b, hipStream_t s);
 }  // namespace mcmg
 

@@ -28,6 +28,7 @@
 // in-plane halos are shared with neighbouring blocks.  The tap loop runs
 // over dz at run time with the 9 in-plane taps unrolled, so at most one
 // plane's weights are live (the fully unrolled 27-tap form spills).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -38,8 +39,11 @@ namespace {
 
 template <int D> struct G1;
 template <> struct G1<2> { static constexpr int TZ = 1, TY = 8, TX = 64; };
-// 3D z-streaming tile: TY x TX nodes per plane, ZC planes per block
-struct G3 { static constexpr int TY = 8, TX = 60, ZC = 32; };
+// 3D z-streaming tile: TY x TX nodes per plane; the planes per block (the
+// z chunk) are chosen at launch.  9 x 54 fills the thread slots of every
+// phase box well (t 13 x 58 in 3 x 256 slots, u 11 x 56 and e 15 x 60 in
+// 3 and 4, the tile 9 x 54 in 2) and divides 216, 108 and 54 in x.
+struct G3 { static constexpr int TY = 9, TX = 54; };
 
 constexpr int NTH = 256;
 
@@ -284,7 +288,8 @@ __device__ __forceinline__ int ring(int pl, int R) { return (pl + 4 * R) % R; }
 // loads from the argument segment) or staged in LDS (batched launches).
 template <int VAR>
 __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, const int vblk) {
-  constexpr int TY = G3::TY, TX = G3::TX, ZC = G3::ZC;
+  constexpr int TY = G3::TY, TX = G3::TX;
+  const int ZC = A.zc;
   constexpr bool STEP = VAR == L1_STEP, FIRST = VAR == L1_FIRST, RESID = VAR == L1_RESID;
   // e box (STEP: halo 3 around the tile; RESID: halo 1); FIRST has e = 0
   constexpr int H = RESID ? 1 : 3;
@@ -532,10 +537,14 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
       if (k + 1 <= k1) load_ra(k);
       __syncthreads();                          // t(k - 1) published
     }
-    // u(p) = s (.) (KS * t), p = k - 1 - LAG, zero outside the grid
+    // u(p) = s (.) (KS * t), p = k - 1 - LAG, zero outside the grid.  The
+    // scatter of input plane q = k - LAG feeds u(q - 1 .. q + 1); the output
+    // phase reads u(zb - 1 .. ze) only, so the first planes of a chunk's
+    // march (STEP: two) are not scattered.
     {
-      scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0, uc1,
-              integral_constant<int, PU>());
+      if (k >= zb - 2 + LAG)
+        scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0, uc1,
+                integral_constant<int, PU>());
       const int p = k - 1 - LAG;
 #pragma unroll
       for (int j = 0; j < PU; ++j) {
@@ -549,10 +558,13 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
       if (k + 1 <= k1) load_s(p + 1);
     }
     __syncthreads();                            // u(p) published; st consumed
-    // out(z) = e + Wsm * u, z = k - 2 - LAG
+    // out(z) = e + Wsm * u, z = k - 2 - LAG.  u(p) feeds out(p - 1 .. p + 1),
+    // so it is scattered only from p = zb - 1 on (the skipped planes' u and
+    // out are discarded, and slots enter the window cleared).
     {
-      scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0, oc1,
-              integral_constant<int, PO>());
+      if (k >= zb + LAG)
+        scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0, oc1,
+                integral_constant<int, PO>());
       const int z = k - 2 - LAG;
       if (z >= zb && z < ze) {
 #pragma unroll
@@ -662,16 +674,41 @@ hipError_t dispatch(const L1Launch& l, const BatchLaunch* b, hipStream_t s) {
 
 }  // namespace
 
-L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk) {
+// Resident blocks per CU of the single-problem 3D kernel of a variant.
+static int l1z_blocks_per_cu(int var) {
+  static int cache[3] = {0, 0, 0};
+  int& n = cache[var];
+  if (n == 0) {
+    int v = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (var == L1_STEP) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, l1z_kernel<L1_STEP>, NTH, 0);
+    if (var == L1_FIRST) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, l1z_kernel<L1_FIRST>, NTH, 0);
+    if (var == L1_RESID) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, l1z_kernel<L1_RESID>, NTH, 0);
+    n = (e == hipSuccess && v > 0) ? v : 2;
+  }
+  return n;
+}
+
+L1Args l1_args(const L1Launch& l, const L1Weights* wdev, int* nblk, int nprob) {
   const int TX = l.dim == 2 ? G1<2>::TX : G3::TX, TY = l.dim == 2 ? G1<2>::TY : G3::TY;
-  const int TZ = l.dim == 2 ? G1<2>::TZ : G3::ZC;
   const int NX = (l.dim == 2) ? l.n.n[1] : l.n.n[2], NY = (l.dim == 2) ? l.n.n[0] : l.n.n[1];
   const int NZ = (l.dim == 2) ? 1 : l.n.n[0];
   L1Args A;
   A.e = l.e; A.eo = l.eo; A.r = l.r; A.a = l.a; A.s = l.s; A.wp = wdev; A.n = l.n;
   A.tiles_x = (NX + TX - 1) / TX;
   A.tiles_y = (NY + TY - 1) / TY;
-  A.tiles_z = (NZ + TZ - 1) / TZ;
+  if (l.dim == 2) {
+    A.zc = 1;
+  } else {
+    // the z chunk: as many chunks per column as fill one wave of resident
+    // blocks (each chunk re-marches 6 planes of halo, so fewer, longer
+    // chunks cost less once the chip is full), at least 4 planes
+    const int cols = A.tiles_x * A.tiles_y;
+    const int slots = l1z_blocks_per_cu(l.var) * device_cus() / std::max(1, nprob);
+    const int chunks = std::max(1, slots / std::max(1, cols));
+    A.zc = std::max(4, (NZ + chunks - 1) / chunks);
+  }
+  A.tiles_z = (NZ + A.zc - 1) / A.zc;
   const int nt = A.tiles_x * A.tiles_y * A.tiles_z;
   *nblk = ((nt + 7) / 8) * 8;
   return A;
