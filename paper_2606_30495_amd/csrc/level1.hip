@@ -298,7 +298,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   // next plane being stored); RESID keeps k and k + 1
   constexpr int NER = STEP ? 5 : 2;
   // t box (halo 2) for STEP / FIRST; RESID computes t on the tile
-  constexpr int TYt = RESID ? TY : TY + 4, TXt = RESID ? TX : TX + 4, NT = TYt * TXt;
+  constexpr int TG = RESID ? 0 : 2;
+  constexpr int TYt = TY + 2 * TG, TXt = TX + 2 * TG, NT = TYt * TXt;
   constexpr int UY = TY + 2, UX = TX + 2, NU = UY * UX;
   constexpr int NO = TY * TX;
   constexpr int PE = (NE + NTH - 1) / NTH, PT = (NT + NTH - 1) / NTH;
@@ -321,34 +322,52 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   const int x0 = (tl % A.tiles_x) * TX, y0 = ((tl / A.tiles_x) % A.tiles_y) * TY;
   const int zb = (tl / (A.tiles_x * A.tiles_y)) * ZC;
   const int ze = min(zb + ZC, NZ);
-  auto inside = [&](int z, int y, int x) {
-    return x >= 0 && x < NX && y >= 0 && y < NY && z >= 0 && z < NZ;
-  };
-  auto gidx = [&](int z, int y, int x) { return ((long long)z * NY + y) * NX + x; };
+  const int plane = NY * NX;
   const float2 zero = make_float2(0.f, 0.f);
+  // A point's position is fixed for the whole march, so its in-plane grid
+  // offset is computed once (-1 outside the grid or for an unused slot) and
+  // a plane only adds a wave-uniform base: plane z of a tensor, clamped into
+  // the grid (a plane outside it is only named by masked loads).
+  auto poff = [&](bool used, int gy, int gx) {
+    return (used && gy >= 0 && gy < NY && gx >= 0 && gx < NX) ? gy * NX + gx : -1;
+  };
+  auto at = [&](auto p, int z) { return p + (long long)min(max(z, 0), NZ - 1) * plane; };
+  auto zin = [&](int z) { return z >= 0 && z < NZ; };
+  // the point's value in plane pz, or zero outside the grid; the load is
+  // unconditional (offset 0 when masked), so the select does not become a
+  // load through a selected pointer
+  auto ld = [&](gptr<const float2> pz, int off, bool zok) {
+    const bool ok = zok && off >= 0;
+    const float2 v = gld(pz, (long long)(unsigned)(ok ? off : 0));
+    return ok ? v : zero;
+  };
 
   // Scatter plane P (pitch = its box width) into the accumulators of the
-  // outputs one behind (slot 0, dz = 2), level (slot 1, dz = 1) and one
-  // ahead (slot 2, dz = 0) of it.  T holds the tap-major weights: per
+  // outputs one behind (logical slot 0, dz = 2), level (slot 1, dz = 1) and
+  // one ahead (slot 2, dz = 0) of it; logical slot q lives in register set
+  // (q + R) % 3, R the phase of the march, so finishing an output renames
+  // the sets instead of moving them.  T holds the tap-major weights: per
   // in-plane tap, per dz, the 2 x 2 channel block X (and, when PAIR, the
   // block Y of a second tensor read from the same values right after it),
   // so one tap's weights are one contiguous run.
-  auto scatter = [&](auto pair, const float2* P, int pitch, const float* T, const int* base,
+  auto scatter = [&](auto rot, auto pair, const float2* P, int pitch, const float* T, const int* base,
                      auto& c0, auto& c1, auto& d0, auto& d1, auto npts) {
+    constexpr int R = decltype(rot)::value;
     constexpr bool PAIR = decltype(pair)::value;
     constexpr int NP = decltype(npts)::value;
     constexpr int TS = PAIR ? 24 : 12;   // floats per in-plane tap
-    // taps at run time: only one tap's 12 (24) weights are live
+    // taps at run time, (dy, dx) row-major from (-1, -1): only one tap's
+    // 12 (24) weights are live
+    int to = -pitch - 1, dx = 0;
 #pragma unroll 1
     for (int t = 0; t < 9; ++t) {
-      const int to = (t / 3 - 1) * pitch + (t % 3 - 1);
       float2 v[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) v[k] = P[base[k] + to];
       const float* wt = T + t * TS;
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz) {
-        const int slot = 2 - dz;
+        const int slot = (2 - dz + R) % 3;
         const float* w = wt + dz * (TS / 3);
         const float a00 = w[0], a01 = w[1], a10 = w[2], a11 = w[3];
 #pragma unroll
@@ -365,48 +384,61 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
           }
         }
       }
+      if (++dx == 3) {
+        dx = 0;
+        to += pitch - 2;
+      } else {
+        ++to;
+      }
     }
   };
-  // slot 0 is finished: move the others down, clear the new one ahead
-  auto shift = [&](auto& c) {
+  // logical slot 0 (set R) is finished: clear it, it becomes the next
+  // phase's slot 2
+  auto clear = [&](auto& c, auto rot) {
+    constexpr int R = decltype(rot)::value;
     constexpr int NP = sizeof(c[0]) / sizeof(float);
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      c[0][k] = c[1][k];
-      c[1][k] = c[2][k];
-      c[2][k] = 0.f;
-    }
+    for (int k = 0; k < NP; ++k) c[R][k] = 0.f;
   };
   using std::integral_constant;
 
   // ---- per-thread points of each box, fixed for the whole march ----------
-  // t box
-  int tb[PT], ty_[PT], tx_[PT];
+  // t box: LDS base of tap (0, 0) in the e box (RESID / STEP), grid offset
+  int tb[PT], toff[PT];
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
     const int i = threadIdx.x + k * NTH;
-    ty_[k] = i / TXt;
-    tx_[k] = i % TXt;
-    // LDS base of tap (0, 0) in the e box (RESID / STEP)
-    tb[k] = (i < NT) ? (ty_[k] + H - (RESID ? 0 : 2)) * EX + (tx_[k] + H - (RESID ? 0 : 2)) : EX + 1;
+    const int ty = i / TXt, tx = i % TXt;
+    tb[k] = (i < NT) ? (ty + H - TG) * EX + (tx + H - TG) : EX + 1;
+    toff[k] = poff(i < NT, y0 - TG + ty, x0 - TG + tx);
   }
-  // u box
-  int ub[PU], uy_[PU], ux_[PU];
+  // u box: LDS base of tap (0, 0) in the t box, grid offset
+  int ub[PU], uoff[PU];
 #pragma unroll
   for (int k = 0; k < PU; ++k) {
     const int i = threadIdx.x + k * NTH;
-    uy_[k] = i / UX;
-    ux_[k] = i % UX;
-    ub[k] = (i < NU) ? (uy_[k] + 1) * TXt + (ux_[k] + 1) : TXt + 1;
+    const int uy = i / UX, ux = i % UX;
+    ub[k] = (i < NU) ? (uy + 1) * TXt + (ux + 1) : TXt + 1;
+    uoff[k] = poff(i < NU, y0 - 1 + uy, x0 - 1 + ux);
   }
-  // output tile
-  int ob[PO], oy_[PO], ox_[PO];
+  // output tile: LDS base of tap (0, 0) in the u box, the point's e in the
+  // e box, grid offset
+  int ob[PO], oe[PO], ooff[PO];
 #pragma unroll
   for (int k = 0; k < PO; ++k) {
     const int i = threadIdx.x + k * NTH;
-    oy_[k] = i / TX;
-    ox_[k] = i % TX;
-    ob[k] = (i < NO) ? (oy_[k] + 1) * UX + (ox_[k] + 1) : UX + 1;
+    const int oy = i / TX, ox = i % TX;
+    ob[k] = (i < NO) ? (oy + 1) * UX + (ox + 1) : UX + 1;
+    oe[k] = (i < NO) ? (oy + H) * EX + (ox + H) : 0;
+    ooff[k] = poff(i < NO, y0 + oy, x0 + ox);
+  }
+  // e box (STEP / RESID): grid offset
+  constexpr int PEB = FIRST ? 1 : PE;
+  int eoff[PEB];
+#pragma unroll
+  for (int k = 0; k < PEB; ++k) {
+    const int i = threadIdx.x + k * NTH;
+    eoff[k] = poff(i < NE, y0 - H + i / EX, x0 - H + i % EX);
   }
 
   // ---- the arriving plane's operands, loaded one iteration ahead ---------
@@ -414,18 +446,11 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   constexpr int PIN = FIRST ? PT : PE;
   float2 vin[PIN];
   auto load_in = [&](int k) {
+    const bool zok = zin(k);
 #pragma unroll
     for (int j = 0; j < PIN; ++j) {
-      if constexpr (FIRST) {
-        const int gy = y0 - 2 + ty_[j], gx = x0 - 2 + tx_[j];
-        const bool ok = threadIdx.x + j * NTH < NT && inside(k, gy, gx);
-        vin[j] = ldz(r, gidx(k, gy, gx), ok);
-      } else {
-        const int i = threadIdx.x + j * NTH;
-        const int gy = y0 - H + i / EX, gx = x0 - H + i % EX;
-        const bool ok = i < NE && inside(k, gy, gx);
-        vin[j] = ldz(e, gidx(k, gy, gx), ok);
-      }
+      if constexpr (FIRST) vin[j] = ld(at(r, k), toff[j], zok);
+      else vin[j] = ld(at(e, k), eoff[j], zok);
     }
   };
   auto store_in = [&](int k) {
@@ -439,14 +464,13 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   };
 
   // ---- accumulators ---------------------------------------------------------
-  float tw0[3][RESID ? PO : PT], tw1[3][RESID ? PO : PT], tk0[3][RESID ? PO : PT],
-      tk1[3][RESID ? PO : PT];
+  float tw0[3][PT], tw1[3][PT], tk0[3][PT], tk1[3][PT];
   float uc0[3][PU], uc1[3][PU];
   float oc0[3][PO], oc1[3][PO];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
 #pragma unroll
-    for (int k = 0; k < (RESID ? PO : PT); ++k) tw0[q][k] = tw1[q][k] = tk0[q][k] = tk1[q][k] = 0.f;
+    for (int k = 0; k < PT; ++k) tw0[q][k] = tw1[q][k] = tk0[q][k] = tk1[q][k] = 0.f;
 #pragma unroll
     for (int k = 0; k < PU; ++k) uc0[q][k] = uc1[q][k] = 0.f;
 #pragma unroll
@@ -454,28 +478,23 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   }
   // operands of the outputs finished next: r, a of the t plane, s of the u
   // plane (loaded after their previous use, consumed one iteration later)
-  constexpr int PR = RESID ? PO : PT;
-  float2 rv[PR], av[PR], sv[PU];
+  float2 rv[PT], av[PT], sv[PU];
   auto load_ra = [&](int q) {
+    const bool zok = zin(q);
 #pragma unroll
-    for (int k = 0; k < PR; ++k) {
-      int gy, gx;
-      bool in;
-      if constexpr (RESID) { gy = y0 + oy_[k]; gx = x0 + ox_[k]; in = threadIdx.x + k * NTH < NO; }
-      else { gy = y0 - 2 + ty_[k]; gx = x0 - 2 + tx_[k]; in = threadIdx.x + k * NTH < NT; }
-      const bool ok = in && inside(q, gy, gx);
-      rv[k] = ldz(r, gidx(q, gy, gx), ok);
-      av[k] = ldz(a, gidx(q, gy, gx), ok);
+    for (int k = 0; k < PT; ++k) {
+      rv[k] = ld(at(r, q), toff[k], zok);
+      av[k] = ld(at(a, q), toff[k], zok);
     }
   };
   auto load_s = [&](int p) {
+    const bool zok = zin(p);
 #pragma unroll
-    for (int k = 0; k < PU; ++k) {
-      const int gy = y0 - 1 + uy_[k], gx = x0 - 1 + ux_[k];
-      const bool ok = threadIdx.x + k * NTH < NU && inside(p, gy, gx);
-      sv[k] = ldz(s, gidx(p, gy, gx), ok);
-    }
+    for (int k = 0; k < PU; ++k) sv[k] = ld(at(s, p), uoff[k], zok);
   };
+  const integral_constant<int, 0> R0;
+  const integral_constant<int, 1> R1;
+  const integral_constant<int, 2> R2;
 
   if constexpr (RESID) {
     // plane k of e feeds t(k - 1), t(k), t(k + 1); t(k - 1) is written
@@ -483,26 +502,33 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     load_in(k0);
     store_in(k0);
     load_ra(k0 - 1);
-    for (int k = k0; k <= k1; ++k) {
+    auto iter = [&](int k, auto rot) {
+      constexpr int R = decltype(rot)::value;
       if (k + 1 <= k1) load_in(k + 1);
       __syncthreads();                          // e(k) in LDS; e(k - 1)'s slot is free
-      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
-              tw0, tw1, tk0, tk1, integral_constant<int, PO>());
+      scatter(rot, integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
+              tw0, tw1, tk0, tk1, integral_constant<int, PT>());
       const int q = k - 1;
       if (q >= zb) {
+        const auto oq = at(eo, q);
 #pragma unroll
-        for (int j = 0; j < PO; ++j) {
-          const int gy = y0 + oy_[j], gx = x0 + ox_[j];
-          if (threadIdx.x + j * NTH < NO && inside(q, gy, gx))
-            gst(eo, gidx(q, gy, gx), make_float2(rv[j].x - tw0[0][j] - av[j].x * tk0[0][j],
-                                                 rv[j].y - tw1[0][j] - av[j].y * tk1[0][j]));
+        for (int j = 0; j < PT; ++j) {
+          if (toff[j] >= 0)
+            gst(oq, (long long)(unsigned)toff[j],
+                make_float2(rv[j].x - tw0[R][j] - av[j].x * tk0[R][j],
+                            rv[j].y - tw1[R][j] - av[j].y * tk1[R][j]));
         }
       }
-      shift(tw0); shift(tw1); shift(tk0); shift(tk1);
+      clear(tw0, rot); clear(tw1, rot); clear(tk0, rot); clear(tk1, rot);
       if (k + 1 <= k1) {
         load_ra(k);
         store_in(k + 1);                        // into the other slot of the pair
       }
+    };
+    for (int k = k0; k <= k1; k += 3) {
+      iter(k, R0);
+      if (k + 1 <= k1) iter(k + 1, R1);
+      if (k + 2 <= k1) iter(k + 2, R2);
     }
     return;
   }
@@ -516,24 +542,25 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   store_in(k0);
   if constexpr (STEP) load_ra(k0 - 1);
   load_s(k0 - 1 - LAG);
-  for (int k = k0; k <= k1; ++k) {
+  auto iter = [&](int k, auto rot) {
+    constexpr int R = decltype(rot)::value;
     if (k + 1 <= k1) load_in(k + 1);
     __syncthreads();                            // input plane k published; su, st free
     if constexpr (STEP) {
-      scatter(integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
+      scatter(rot, integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
               tw0, tw1, tk0, tk1, integral_constant<int, PT>());
       // t(k - 1) = r - W e - a (.) (KA e), zero outside the grid
-      const int q = k - 1;
+      const bool qin = zin(k - 1);
 #pragma unroll
       for (int j = 0; j < PT; ++j) {
         const int i = threadIdx.x + j * NTH;
         if (i < NT)
-          st[i] = inside(q, y0 - 2 + ty_[j], x0 - 2 + tx_[j])
-                      ? make_float2(rv[j].x - tw0[0][j] - av[j].x * tk0[0][j],
-                                    rv[j].y - tw1[0][j] - av[j].y * tk1[0][j])
+          st[i] = (qin && toff[j] >= 0)
+                      ? make_float2(rv[j].x - tw0[R][j] - av[j].x * tk0[R][j],
+                                    rv[j].y - tw1[R][j] - av[j].y * tk1[R][j])
                       : zero;
       }
-      shift(tw0); shift(tw1); shift(tk0); shift(tk1);
+      clear(tw0, rot); clear(tw1, rot); clear(tk0, rot); clear(tk1, rot);
       if (k + 1 <= k1) load_ra(k);
       __syncthreads();                          // t(k - 1) published
     }
@@ -543,18 +570,17 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     // march (STEP: two) are not scattered.
     {
       if (k >= zb - 2 + LAG)
-        scatter(integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0, uc1,
-                integral_constant<int, PU>());
+        scatter(rot, integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0,
+                uc1, integral_constant<int, PU>());
       const int p = k - 1 - LAG;
+      const bool pin = zin(p);
 #pragma unroll
       for (int j = 0; j < PU; ++j) {
         const int i = threadIdx.x + j * NTH;
         if (i < NU)
-          su[i] = inside(p, y0 - 1 + uy_[j], x0 - 1 + ux_[j])
-                      ? make_float2(sv[j].x * uc0[0][j], sv[j].y * uc1[0][j])
-                      : zero;
+          su[i] = (pin && uoff[j] >= 0) ? make_float2(sv[j].x * uc0[R][j], sv[j].y * uc1[R][j]) : zero;
       }
-      shift(uc0); shift(uc1);
+      clear(uc0, rot); clear(uc1, rot);
       if (k + 1 <= k1) load_s(p + 1);
     }
     __syncthreads();                            // u(p) published; st consumed
@@ -563,27 +589,31 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     // out are discarded, and slots enter the window cleared).
     {
       if (k >= zb + LAG)
-        scatter(integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0, oc1,
-                integral_constant<int, PO>());
+        scatter(rot, integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0,
+                oc1, integral_constant<int, PO>());
       const int z = k - 2 - LAG;
       if (z >= zb && z < ze) {
+        const auto oz = at(eo, z);
 #pragma unroll
         for (int j = 0; j < PO; ++j) {
-          const int i = threadIdx.x + j * NTH;
-          const int gy = y0 + oy_[j], gx = x0 + ox_[j];
-          if (i < NO && inside(z, gy, gx)) {
+          if (ooff[j] >= 0) {
             float2 ev = zero;
-            if (STEP) ev = se[ring(z, NER) * NE + (oy_[j] + H) * EX + (ox_[j] + H)];
-            gst(eo, gidx(z, gy, gx), make_float2(ev.x + oc0[0][j], ev.y + oc1[0][j]));
+            if (STEP) ev = se[ring(z, NER) * NE + oe[j]];
+            gst(oz, (long long)(unsigned)ooff[j], make_float2(ev.x + oc0[R][j], ev.y + oc1[R][j]));
           }
         }
       }
-      shift(oc0); shift(oc1);
+      clear(oc0, rot); clear(oc1, rot);
       // the next input plane: its slot held e(k - 4) (STEP), read by the
       // previous iteration's output phase; FIRST's r plane was last read by
       // this iteration's u phase, finished at the barrier above
       if (k + 1 <= k1) store_in(k + 1);
     }
+  };
+  for (int k = k0; k <= k1; k += 3) {
+    iter(k, R0);
+    if (k + 1 <= k1) iter(k + 1, R1);
+    if (k + 2 <= k1) iter(k + 2, R2);
   }
 }
 
