@@ -30,7 +30,12 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int ZTX = 16, ZTY = 8;               // output column of a block
 constexpr int ZHX = ZTX + 2, ZHY = ZTY + 2;    // staged plane with its halo
 constexpr int ZPN = ZHX * ZHY;                 // nodes of a staged plane
-constexpr int ZC = 12, ZST = ZC + 1;           // channels, LDS node stride
+// LDS node stride: unpadded.  A fragment read has lane (li, lg) read
+// channel 4 cq + lg of node li; with 12 floats per node the 16 nodes start
+// on 16 distinct multiples of 4 banks, so the 64 lanes hit 64 distinct
+// banks (a 13-float stride puts up to four lanes on one bank), and a
+// channel quad is one 16-byte store when the plane is staged.
+constexpr int ZC = 12, ZST = ZC;               // channels, LDS node stride
 constexpr int ZPLANE = ZPN * ZST;              // floats of a ring slot
 constexpr int ZSTEPS = 27 * ZC / 4;            // 81 K steps
 constexpr int ZSTEPS4 = (ZSTEPS + 3) / 4 * 4;  // 84: whole runs of four steps
@@ -83,20 +88,29 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
   }
 
   // ---- planes: element idx of a plane is (node idx / 3, channel quad idx % 3)
-  // of the staged 18 x 10 box; nodes outside the grid are zero.  The loads
-  // are unconditional (clamped index, value selected afterwards).
+  // of the staged 18 x 10 box; nodes outside the grid are zero.  A thread's
+  // elements are the same in every plane, so their in-plane grid offsets are
+  // computed once (-1 outside the grid); a plane adds a uniform base.  The
+  // loads are unconditional (offset 0 when masked, value selected after).
+  const long long pin = (long long)NY * NX * ZC;      // floats of an input plane
+  int poff[ZPF];
+#pragma unroll
+  for (int k = 0; k < ZPF; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    const int node = idx / 3, c = (idx - 3 * node) * 4;
+    const int hy = node / ZHX, hx = node - hy * ZHX;
+    const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
+    const bool ok = (idx < ZPN * 3) & ((unsigned)gx < (unsigned)NX) & ((unsigned)gy < (unsigned)NY);
+    poff[k] = ok ? (gy * NX + gx) * ZC + c : -1;
+  }
   float4 pf[ZPF];
   auto load_plane = [&](int z) {
+    const bool zok = (unsigned)z < (unsigned)NZ;
+    const gptr<const float> xz = x + (zok ? z : 0) * pin;
 #pragma unroll
     for (int k = 0; k < ZPF; ++k) {
-      const int idx = threadIdx.x + 256 * k;
-      const int node = idx / 3, c = (idx - 3 * node) * 4;
-      const int hy = node / ZHX, hx = node - hy * ZHX;
-      const int gx = x0 - 1 + hx, gy = y0 - 1 + hy;
-      const bool ok = (idx < ZPN * 3) & ((unsigned)gx < (unsigned)NX) & ((unsigned)gy < (unsigned)NY) &
-                      ((unsigned)z < (unsigned)NZ);
-      const long long g = ok ? (((long long)z * NY + gy) * NX + gx) * ZC + c : 0;
-      const float4 v = gld((gptr<const float4>)(x + g), 0);
+      const bool ok = zok && poff[k] >= 0;
+      const float4 v = gld((gptr<const float4>)(xz + (unsigned)(ok ? poff[k] : 0)), 0);
       pf[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
@@ -105,10 +119,7 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
 #pragma unroll
     for (int k = 0; k < ZPF; ++k) {
       const int idx = threadIdx.x + 256 * k;
-      if (idx >= ZPN * 3) continue;
-      const int node = idx / 3, c = (idx - 3 * node) * 4;
-      float* sp = slot + node * ZST + c;
-      sp[0] = pf[k].x; sp[1] = pf[k].y; sp[2] = pf[k].z; sp[3] = pf[k].w;
+      if (idx < ZPN * 3) *reinterpret_cast<float4*>(slot + 4 * idx) = pf[k];   // node idx / 3, channels 4 (idx % 3)
     }
   };
   load_plane(z0 - 1);
@@ -125,13 +136,22 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
   for (int i = 0; i < 2; ++i) lbase[i] = ((wave + 4 * i) * ZHX + li) * ZST + lg;
   const int blane = (lg * 16 + li) * 4;
 
-  // output offset of accumulator element (row i, r): node (x0 + 4 lg + r,
-  // y0 + w + 4 i, z), column li; -1 outside the grid or the channels
-  auto out_off = [&](int i, int rr, int z) -> long long {
-    const int gx = x0 + 4 * lg + rr, gy = y0 + wave + 4 * i;
-    if (li < cout && gx < NX && gy < NY) return (((long long)z * NY + gy) * NX + gx) * cout + li;
-    return -1;
-  };
+  // accumulator element (row i, r) is node (x0 + 4 lg + r, y0 + w + 4 i),
+  // column li: its in-plane output offset is obase[i] + r cout; the row is
+  // in the grid when rowok[i] (wave-uniform), the element when also
+  // 4 lg + r < NX - x0 and li < cout
+  const long long pout = (long long)NY * NX * cout;   // floats of an output plane
+  int obase[2];
+  bool rowok[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int gy = y0 + wave + 4 * i;
+    rowok[i] = gy < NY;
+    obase[i] = (min(gy, NY - 1) * NX + x0 + 4 * lg) * cout + li;
+  }
+  const int xlim = NX - x0 - 4 * lg;                  // element r is in the grid when r < xlim
+  const bool colok = li < cout;
+  auto elem_ok = [&](int i, int rr) { return rowok[i] && colok && rr < xlim; };
 
   for (int z = z0; z < z1; ++z) {
     __syncthreads();              // planes z - 1 .. z + 1 (and the weights) published
@@ -141,18 +161,19 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
       store_plane(z + 2);
       if (z + 2 < z1) load_plane(z + 3);
     }
-    // epilogue operands of plane z: in flight during the K loop
+    // epilogue operands of plane z: in flight during the K loop (the loads
+    // are unconditional, offset 0 outside the grid)
+    const long long zo = (long long)z * pout;
     float e0[2][4], e1[2][4];
     if constexpr (EPI != EPI_SET) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const long long o = out_off(i, rr, z);
-          const long long oc = o >= 0 ? o : 0;
-          if (EPI == EPI_ADD) e0[i][rr] = y[oc];
-          else if (EPI == EPI_MUL) e0[i][rr] = feat[oc];
-          else { e0[i][rr] = r[oc]; e1[i][rr] = feat[oc]; }
+          const unsigned oc = elem_ok(i, rr) ? (unsigned)(obase[i] + rr * cout) : 0u;
+          if (EPI == EPI_ADD) e0[i][rr] = (y + zo)[oc];
+          else if (EPI == EPI_MUL) e0[i][rr] = (feat + zo)[oc];
+          else { e0[i][rr] = (r + zo)[oc]; e1[i][rr] = (feat + zo)[oc]; }
         }
     }
     const int sb[3] = {((z - 1 + NS) % NS) * ZPLANE, (z % NS) * ZPLANE, ((z + 1) % NS) * ZPLANE};
@@ -207,13 +228,11 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const long long o = out_off(i, rr, z);
-        if (o < 0) continue;
         float v = acc[0][i][rr];
         if (EPI == EPI_ADD) v = e0[i][rr] + v;
         else if (EPI == EPI_MUL) v = e0[i][rr] * v;
         else if (EPI == EPI_RESID) v = e0[i][rr] - v - e1[i][rr] * acc[NACC - 1][i][rr];
-        y[o] = v;
+        if (elem_ok(i, rr)) (y + zo)[(unsigned)(obase[i] + rr * cout)] = v;
       }
     if (NS == 3 && z + 1 < z1) {
       __syncthreads();            // every wave is done with plane z - 1's slot
