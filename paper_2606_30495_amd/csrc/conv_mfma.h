@@ -44,9 +44,10 @@ MArgs mfma_args(const MfmaConv& a, int* nblk);
 hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b, hipStream_t s);
 
 // Zero K steps stored after every packed weight tensor: the 3D float32
-// kernels load B fragments in groups of four steps, up to three groups past
-// the last step they multiply, without a bounds clamp.
-constexpr int MFMA_PAD_STEPS = 16;
+// kernels load B fragments in groups of four steps, up to 2 NB - 1 groups
+// past the last group they multiply (NB <= 8 register sets), without a
+// bounds clamp.
+constexpr int MFMA_PAD_STEPS = 64;
 
 // 3D float32 weights are packed by groups of four K steps, so that a lane
 // reads the B values of a whole group as one 16-byte vector: pair q (K step

@@ -135,7 +135,13 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
   const int ks0 = nsteps < kchunk ? nsteps : kchunk;
   if constexpr (!BG) wfetch(0, ks0, bsm);
   constexpr int GS = 4;   // K steps per group of B loads (float32)
-  float bq0[GS][NACC][NTW], bq1[GS][NACC][NTW];   // unused unless BG
+  // B register sets: group j sits in set j % NB and is requested NB groups
+  // before its products, about 32 matrix products ahead whatever the tile
+  // (an L2 round trip is longer than the 8 products of two one-row groups)
+  constexpr int PERG = GS * MT * NTW * RPW * NACC;   // products per group
+  constexpr int NB = !BG ? 1 : PERG >= 16 ? 2 : PERG >= 8 ? 4 : 8;
+  static_assert(!BG || MFMA_PAD_STEPS >= (2 * NB - 2) * GS + 4, "look-ahead past the zero steps");
+  float bq[NB][GS][NACC][NTW];   // unused unless BG
   // B fragments of the group of four steps s0 .. s0 + 3 (s0 a multiple of
   // 4), tile t: with the weights packed by step groups (mfma_bg_index) they
   // are one 16-byte vector per lane and tensor, at vector (s0 + lg) ncols +
@@ -158,8 +164,8 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
       }
   };
   if constexpr (BG) {
-    loadB(0, bq0);
-    loadB(GS, bq1);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) loadB(b * GS, bq[b]);
   }
 
   // ---- stage the input tile: loads are issued in batches of SB per thread
@@ -424,19 +430,18 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
           }
         }
       };
-      Frag aq0[GS][RPW][MT], aq1[GS][RPW][MT];
-      loadAq(aq0);
-      for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
-        loadAq(aq1);
+      Frag aq[2][GS][RPW][MT];
+      loadAq(aq[0]);
+      for (int s0 = 0; s0 < nsteps; s0 += NB * GS) {
 #pragma unroll
-        for (int g = 0; g < GS; ++g) mma(bq0[g], aq0[g]);
-        loadB(s0 + 2 * GS, bq0);
-        loadAq(aq0);
-        if (s0 + GS < nsteps) {
+        for (int b = 0; b < NB; ++b) {
+          loadAq(aq[(b + 1) & 1]);
+          if (b == 0 || s0 + b * GS < nsteps) {
 #pragma unroll
-          for (int g = 0; g < GS; ++g) mma(bq1[g], aq1[g]);
+            for (int g = 0; g < GS; ++g) mma(bq[b][g], aq[b & 1][g]);
+          }
+          loadB(s0 + (b + NB) * GS, bq[b]);
         }
-        loadB(s0 + 3 * GS, bq1);
       }
     } else {
       int s_cb = 0, s_dx = 0, s_dy = 0, s_toff = 0, s_k = 0;
@@ -481,11 +486,12 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
       // zero steps stored after the tensor, or the tile's last step): every
       // path through the loop then has the same loads in flight, so the
       // compiler's counter waits stay exact instead of assuming a skipped load
-      for (int s0 = 0; s0 < nsteps; s0 += 2 * GS) {
-        group(s0, bq0);
-        loadB(s0 + 2 * GS, bq0);
-        if (s0 + GS < nsteps) group(s0 + GS, bq1);
-        loadB(s0 + 3 * GS, bq1);
+      for (int s0 = 0; s0 < nsteps; s0 += NB * GS) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          if (b == 0 || s0 + b * GS < nsteps) group(s0 + b * GS, bq[b]);
+          loadB(s0 + (b + NB) * GS, bq[b]);
+        }
       }
     }
   } else {
