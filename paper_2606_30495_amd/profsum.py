@@ -5,6 +5,7 @@
         --cal-fetch <dir> --cal-write <dir> --cal-bytes B
         [--kernel NAME=SOURCE ...] [--src NAME_PREFIX=SOURCE ...]
 
+    python3 -m paper_2606_30495_amd.profsum periter <kernel_trace.csv> <marker kernel> [n]
     python3 -m paper_2606_30495_amd.profsum mfma <dir> [prefix ...]
     python3 -m paper_2606_30495_amd.profsum counters <dir> [prefix ...]
 
@@ -14,6 +15,11 @@ SQ_INSTS_VALU_MFMA_MOPS_F32, counted in units of 512 flops) per kernel name
 mstep_kernel): dispatches, mean matrix-core flops per dispatch as counted
 by the hardware, mean dispatch duration, flops over duration, and
 MfmaUtil, the matrix-core busy cycles over the busy cycles of all SIMDs.
+
+`periter` splits a kernel trace at the dispatches of a marker kernel
+launched once per iteration (the last n + 1 of them, default n = 10) and
+prints, per kernel name and grid size (blocks), the mean time per
+iteration, the launches per iteration and the mean launch duration.
 
 `counters` prints, per kernel name (those starting with one of the
 prefixes, default all), the dispatch count and the mean per dispatch of
@@ -127,6 +133,31 @@ def replay_run(trace, kernel):
             f"{sum(dur) / len(dur) / 1e3:.3f} us, mean start-to-start {span / len(best) / 1e3:.3f} us")
 
 
+def per_iteration(trace, marker, n=10):
+    rows = list(csv.DictReader(open(trace)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    idx = [i for i, r in enumerate(rows) if short(r["Kernel_Name"]) == marker]
+    if len(idx) < 2:
+        return f"fewer than two dispatches of `{marker}`"
+    seg = idx[-(n + 1):]
+    n = len(seg) - 1
+    tot, cnt = {}, {}
+    for a, b in zip(seg[:-1], seg[1:]):
+        for r in rows[a + 1:b + 1]:
+            blocks = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]) // max(
+                1, int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"]))
+            k = (short(r["Kernel_Name"]), blocks)
+            tot[k] = tot.get(k, 0) + int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+            cnt[k] = cnt.get(k, 0) + 1
+    wall = int(rows[seg[-1]]["End_Timestamp"]) - int(rows[seg[0]]["End_Timestamp"])
+    out = [f"{n} iterations (from one `{marker}` to the next): kernel time "
+           f"{sum(tot.values()) / n / 1e3:.1f} us per iteration, wall {wall / n / 1e3:.1f} us", "",
+           "| kernel | blocks | us per iteration | launches per iteration | avg us |", "|---|---|---|---|---|"]
+    for k in sorted(tot, key=lambda k: -tot[k]):
+        out.append(f"| `{k[0]}` | {k[1]} | {tot[k] / n / 1e3:.1f} | {cnt[k] / n:.1f} | {tot[k] / cnt[k] / 1e3:.1f} |")
+    return "\n".join(out)
+
+
 def counters(d, prefixes):
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     per = {}
@@ -203,6 +234,9 @@ def main(argv):
         return
     if argv[0] == "counters":
         print(counters(argv[1], argv[2:]))
+        return
+    if argv[0] == "periter":
+        print(per_iteration(argv[1], argv[2], int(argv[3]) if len(argv) > 3 else 10))
         return
     if argv[0] == "replay":
         print(replay_run(argv[1], argv[2]))
