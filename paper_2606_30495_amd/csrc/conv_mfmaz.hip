@@ -76,17 +76,6 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
 
-  // ---- the weights: the first ZSTEPS4 steps of each packed tensor, as is
-  {
-    const gptr<const float4> wa = (gptr<const float4>)A.wA;
-    const gptr<const float4> wb = (gptr<const float4>)A.wB;
-    constexpr int NV = ZBTEN / 4;
-    for (int i = threadIdx.x; i < NACC * NV; i += 256) {
-      const float4 v = gld(i < NV ? wa : wb, (long long)(i < NV ? i : i - NV));
-      *reinterpret_cast<float4*>(bs + 4 * i) = v;
-    }
-  }
-
   // ---- planes: element idx of a plane is (node idx / 3, channel quad idx % 3)
   // of the staged 18 x 10 box; nodes outside the grid are zero.  A thread's
   // elements are the same in every plane, so their in-plane grid offsets are
@@ -104,31 +93,53 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
     poff[k] = ok ? (gy * NX + gx) * ZC + c : -1;
   }
   float4 pf[ZPF];
-  auto load_plane = [&](int z) {
+  auto load_plane = [&](int z, float4 (&dst)[ZPF]) {
     const bool zok = (unsigned)z < (unsigned)NZ;
     const gptr<const float> xz = x + (zok ? z : 0) * pin;
 #pragma unroll
     for (int k = 0; k < ZPF; ++k) {
       const bool ok = zok && poff[k] >= 0;
       const float4 v = gld((gptr<const float4>)(xz + (unsigned)(ok ? poff[k] : 0)), 0);
-      pf[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      dst[k] = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  auto store_plane = [&](int z) {
+  auto store_plane = [&](int z, const float4 (&src)[ZPF]) {
     float* slot = ring + ((z + NS) % NS) * ZPLANE;
 #pragma unroll
     for (int k = 0; k < ZPF; ++k) {
       const int idx = threadIdx.x + 256 * k;
-      if (idx < ZPN * 3) *reinterpret_cast<float4*>(slot + 4 * idx) = pf[k];   // node idx / 3, channels 4 (idx % 3)
+      if (idx < ZPN * 3) *reinterpret_cast<float4*>(slot + 4 * idx) = src[k];   // node idx / 3, channels 4 (idx % 3)
     }
   };
-  load_plane(z0 - 1);
-  store_plane(z0 - 1);
-  load_plane(z0);
-  store_plane(z0);
-  load_plane(z0 + 1);
-  store_plane(z0 + 1);
-  load_plane(z0 + 2);           // stays in registers until plane z0 is done
+  // ---- prologue: the weights (the first ZSTEPS4 steps of each packed
+  // tensor, as is) and the first three planes are requested together and
+  // only then stored, so a block waits for one memory latency, not four;
+  // the fourth plane stays in registers until plane z0 is done
+  {
+    const gptr<const float4> wa = (gptr<const float4>)A.wA;
+    const gptr<const float4> wb = (gptr<const float4>)A.wB;
+    constexpr int NV = ZBTEN / 4;
+    constexpr int NW = (NACC * NV + 255) / 256;
+    float4 wv[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int i = min((int)threadIdx.x + 256 * k, NACC * NV - 1);
+      wv[k] = gld(i < NV ? wa : wb, (long long)(i < NV ? i : i - NV));
+    }
+    float4 p0[ZPF], p1[ZPF], p2[ZPF];
+    load_plane(z0 - 1, p0);
+    load_plane(z0, p1);
+    load_plane(z0 + 1, p2);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (i < NACC * NV) *reinterpret_cast<float4*>(bs + 4 * i) = wv[k];
+    }
+    store_plane(z0 - 1, p0);
+    store_plane(z0, p1);
+    store_plane(z0 + 1, p2);
+  }
+  load_plane(z0 + 2, pf);
 
   // this lane's part of the A and B addresses; row i of the wave is y = w + 4 i
   int lbase[2];
@@ -158,8 +169,8 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
     if (NS == 4 && z + 1 < z1) {
       // plane z + 2 into the fourth slot (its plane z - 2 was last read
       // before the barrier above), the plane after it requested
-      store_plane(z + 2);
-      if (z + 2 < z1) load_plane(z + 3);
+      store_plane(z + 2, pf);
+      if (z + 2 < z1) load_plane(z + 3, pf);
     }
     // epilogue operands of plane z: in flight during the K loop (the loads
     // are unconditional, offset 0 outside the grid)
@@ -236,8 +247,8 @@ __device__ __forceinline__ void mconvz_body(const MArgs& A, const int vblk) {
       }
     if (NS == 3 && z + 1 < z1) {
       __syncthreads();            // every wave is done with plane z - 1's slot
-      store_plane(z + 2);         // into that slot
-      if (z + 2 < z1) load_plane(z + 3);
+      store_plane(z + 2, pf);     // into that slot
+      if (z + 2 < z1) load_plane(z + 3, pf);
     }
   }
 }
