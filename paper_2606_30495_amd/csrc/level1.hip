@@ -356,15 +356,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     constexpr bool PAIR = decltype(pair)::value;
     constexpr int NP = decltype(npts)::value;
     constexpr int TS = PAIR ? 24 : 12;   // floats per in-plane tap
-    // taps at run time, (dy, dx) row-major from (-1, -1): only one tap's
-    // 12 (24) weights are live
-    int to = -pitch - 1, dx = 0;
-#pragma unroll 1
-    for (int t = 0; t < 9; ++t) {
-      float2 v[NP];
-#pragma unroll
-      for (int k = 0; k < NP; ++k) v[k] = P[base[k] + to];
-      const float* wt = T + t * TS;
+    // one tap's products on values v (weights wt of the tap)
+    auto tap = [&](const float2 (&v)[NP], const float* wt) {
 #pragma unroll
       for (int dz = 0; dz < 3; ++dz) {
         const int slot = (2 - dz + R) % 3;
@@ -384,14 +377,42 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
           }
         }
       }
-      if (++dx == 3) {
-        dx = 0;
-        to += pitch - 2;
-      } else {
-        ++to;
+    };
+    if constexpr (PAIR) {
+      // taps at run time, (dy, dx) row-major from (-1, -1): only one tap's
+      // 24 weights are live
+      int to = -pitch - 1, dx = 0;
+#pragma unroll 1
+      for (int t = 0; t < 9; ++t) {
+        float2 v[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) v[k] = P[base[k] + to];
+        tap(v, T + t * TS);
+        if (++dx == 3) {
+          dx = 0;
+          to += pitch - 2;
+        } else {
+          ++to;
+        }
+      }
+    } else {
+      // one tap row per iteration: its three taps' values are requested
+      // together, so the row waits once for its loads (36 weights live);
+      // each accumulator still takes the taps in row-major order
+#pragma unroll 1
+      for (int dy = 0; dy < 3; ++dy) {
+        const int ro = (dy - 1) * pitch - 1;
+        float2 v[3][NP];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+          for (int k = 0; k < NP; ++k) v[dx][k] = P[base[k] + ro + dx];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) tap(v[dx], T + (3 * dy + dx) * TS);
       }
     }
   };
+
   // logical slot 0 (set R) is finished: clear it, it becomes the next
   // phase's slot 2
   auto clear = [&](auto& c, auto rot) {
