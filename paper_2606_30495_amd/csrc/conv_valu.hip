@@ -14,6 +14,7 @@
 //   RESID (t = r - W * e - a (.) (KA * e), two weight tensors at once).
 // The batched form runs the same convolution for several problems (own
 // pointers and grids) in one launch.
+#include <algorithm>
 #include <string>
 
 #include "internal.h"
@@ -130,13 +131,17 @@ __global__ __launch_bounds__(256) void conv_direct_batched(const DArgs* __restri
 }
 
 // 3D stride-1 2 -> 2 channel convolution (lift and projection) in the
-// z-streaming form of the level-1 sweep: a block owns a C2Y x C2X column and a
-// chunk of C2Z planes, keeps three input planes (halo 1 in y and x) in an LDS
+// z-streaming form of the level-1 sweep: a block owns a C3Y x C3X column and a
+// chunk of zc planes, keeps three input planes (halo 1 in y and x) in an LDS
 // ring and writes one output plane per step, so every input value is read
 // once per block instead of once per tap.  Each output sums the same products
 // in the same order as conv_body (taps dz-major, then input channel; zero
 // outside the grid).
-constexpr int C2Y = 8, C2X = 64, C2Z = 8;
+// 9 x 54: 486 outputs in 2 x 256 thread slots, the halo plane 11 x 56 in 3,
+// and 54 divides 216, 108 and 54 (a 64-wide tile runs 256 columns for 216).
+// The planes per block are chosen at launch (A.zc).
+constexpr int C3Y = 9, C3X = 54;
+constexpr int C2X = 64;   // 2D tile width
 
 __device__ __forceinline__ int ring3(int pl) { return (pl + 12) % 3; }
 
@@ -145,30 +150,31 @@ bool c22z_ok(const ConvLaunch& a) {
          a.cpad == 2;
 }
 
-void c22z_tiles(const Dims& out, int* tx, int* ty, int* tz) {
-  *tx = (out.n[2] + C2X - 1) / C2X;
-  *ty = (out.n[1] + C2Y - 1) / C2Y;
-  *tz = (out.n[0] + C2Z - 1) / C2Z;
+void c22z_tiles(const Dims& out, int zc, int* tx, int* ty, int* tz) {
+  *tx = (out.n[2] + C3X - 1) / C3X;
+  *ty = (out.n[1] + C3Y - 1) / C3Y;
+  *tz = (out.n[0] + zc - 1) / zc;
 }
 
 template <typename TIN, typename TOUT>
 __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
-  constexpr int EY = C2Y + 2, EX = C2X + 2, NE = EY * EX;
-  constexpr int PE = (NE + 255) / 256, NO = C2Y * C2X, PO = (NO + 255) / 256;
+  constexpr int EY = C3Y + 2, EX = C3X + 2, NE = EY * EX;
+  constexpr int PE = (NE + 255) / 256, NO = C3Y * C3X, PO = (NO + 255) / 256;
   __shared__ float2 se[3 * NE];
   __shared__ float4 sw[27];                 // [tap] (w00, w01, w10, w11)
   const gptr<const TIN> __restrict__ x = to_global<const TIN>(A.x);
   const gptr<TOUT> __restrict__ y = to_global<TOUT>(A.y);
   const gptr<const float> __restrict__ w = to_global<const float>(A.w);
   const int NZ = A.out.n[0], NY = A.out.n[1], NX = A.out.n[2];
-  const int tiles_x = (NX + C2X - 1) / C2X, tiles_y = (NY + C2Y - 1) / C2Y;
-  const int ntiles = tiles_x * tiles_y * ((NZ + C2Z - 1) / C2Z);
+  const int zc = A.zc;
+  const int tiles_x = (NX + C3X - 1) / C3X, tiles_y = (NY + C3Y - 1) / C3Y;
+  const int ntiles = tiles_x * tiles_y * ((NZ + zc - 1) / zc);
   const int per = (ntiles + 7) / 8;
   const int tl = (vblk % 8) * per + vblk / 8;   // XCD-contiguous bands
   if (tl >= ntiles) return;
-  const int x0 = (tl % tiles_x) * C2X, y0 = ((tl / tiles_x) % tiles_y) * C2Y;
-  const int zb = (tl / (tiles_x * tiles_y)) * C2Z;
-  const int ze = min(zb + C2Z, NZ);
+  const int x0 = (tl % tiles_x) * C3X, y0 = ((tl / tiles_x) % tiles_y) * C3Y;
+  const int zb = (tl / (tiles_x * tiles_y)) * zc;
+  const int ze = min(zb + zc, NZ);
   auto inside = [&](int z, int yy, int xx) {
     return xx >= 0 && xx < NX && yy >= 0 && yy < NY && z >= 0 && z < NZ;
   };
@@ -178,18 +184,34 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
   if (threadIdx.x < 27)
     sw[threadIdx.x] = make_float4(w[threadIdx.x * 4 + 0], w[threadIdx.x * 4 + 1],
                                   w[threadIdx.x * 4 + 2], w[threadIdx.x * 4 + 3]);
+  // a thread's points are the same in every plane: their in-plane offsets
+  // (-1 outside the grid) are computed once, a plane adds a uniform base
+  const long long plane = (long long)NY * NX;
+  int eoff[PE], ooff[PO];
+#pragma unroll
+  for (int j = 0; j < PE; ++j) {
+    const int i = threadIdx.x + j * 256;
+    const int yy = y0 - 1 + i / EX, xx = x0 - 1 + i % EX;
+    eoff[j] = (i < NE && inside(0, yy, xx)) ? yy * NX + xx : -1;
+  }
+#pragma unroll
+  for (int j = 0; j < PO; ++j) {
+    const int i = threadIdx.x + j * 256;
+    const int yy = y0 + i / C3X, xx = x0 + i % C3X;
+    ooff[j] = (i < NO && inside(0, yy, xx)) ? yy * NX + xx : -1;
+  }
   // input plane k (halo 1), loaded one plane ahead of its store
   float2 v[PE];
   // (unconditional loads from a clamped index, zero selected afterwards, so
   // all of a plane's loads are in flight together)
   auto load_plane = [&](int k) {
+    const bool zok = k >= 0 && k < NZ;
+    const gptr<const TIN> xk = x + 2 * (zok ? k : 0) * plane;
 #pragma unroll
     for (int j = 0; j < PE; ++j) {
-      const int i = threadIdx.x + j * 256;
-      const int yy = y0 - 1 + i / EX, xx = x0 - 1 + i % EX;
-      const bool ok = i < NE && inside(k, yy, xx);
-      const long long g = ok ? gidx(k, yy, xx) : 0;
-      const float v0 = load_as_f32(x, 2 * g), v1 = load_as_f32(x, 2 * g + 1);
+      const bool ok = zok && eoff[j] >= 0;
+      const unsigned g = ok ? (unsigned)eoff[j] : 0u;
+      const float v0 = load_as_f32(xk, 2ll * g), v1 = load_as_f32(xk, 2ll * g + 1);
       v[j] = ok ? make_float2(v0, v1) : make_float2(0.f, 0.f);
     }
   };
@@ -211,7 +233,7 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
       for (int j = 0; j < PO; ++j) {
         const int i = threadIdx.x + j * 256;
         a0[j] = a1[j] = 0.f;
-        eb[j] = (i < NO) ? (i / C2X) * EX + (i % C2X) : 0;   // tap (0, 0, 0) of the halo-1 plane
+        eb[j] = (i < NO) ? (i / C3X) * EX + (i % C3X) : 0;   // tap (0, 0, 0) of the halo-1 plane
       }
 #pragma unroll 1
       for (int dz = 0; dz < 3; ++dz) {
@@ -230,14 +252,13 @@ __device__ __forceinline__ void c22z_body(const DArgs& A, const int vblk) {
           }
         }
       }
+      const gptr<TOUT> yz = y + 2 * z * plane;
 #pragma unroll
       for (int j = 0; j < PO; ++j) {
-        const int i = threadIdx.x + j * 256;
-        const int yy = y0 + i / C2X, xx = x0 + i % C2X;
-        if (i < NO && inside(z, yy, xx)) {
-          const long long g = gidx(z, yy, xx);
-          store_from_f32(y, 2 * g, a0[j]);
-          store_from_f32(y, 2 * g + 1, a1[j]);
+        if (ooff[j] >= 0) {
+          const long long g = (unsigned)ooff[j];
+          store_from_f32(yz, 2 * g, a0[j]);
+          store_from_f32(yz, 2 * g + 1, a1[j]);
         }
       }
     }
@@ -452,6 +473,7 @@ int conv_chunk(int cout) { return cout <= 2 ? 2 : 8; }
 
 DArgs conv_args(const ConvLaunch& a, int* nblk) {
   DArgs A;
+  A.zc = 1;
   A.x = a.x; A.w = a.w; A.w2 = a.w2; A.y = a.y; A.r = a.r; A.feat = a.feat;
   A.cin = a.cin; A.cout = a.cout; A.cpad = a.cpad; A.in = a.in; A.out = a.out;
   A.fo1 = make_fastdiv((uint32_t)a.out.n[1]);
@@ -461,8 +483,12 @@ DArgs conv_args(const ConvLaunch& a, int* nblk) {
   if (c22y_ok(a) && c22_types) {
     *nblk = ((c22y_tiles(a.out) + 7) / 8) * 8;
   } else if (c22z_ok(a) && c22_types) {
+    // 8-plane chunks: this memory-bound sweep runs faster with more, shorter
+    // blocks (2592 at 216^3, about 1.3 rounds of resident blocks) than with
+    // chunks sized to one round (1920 blocks: 82 vs 78 us for the lift)
     int tx, ty, tz;
-    c22z_tiles(a.out, &tx, &ty, &tz);
+    A.zc = 8;
+    c22z_tiles(a.out, A.zc, &tx, &ty, &tz);
     const int nt = tx * ty * tz;
     *nblk = ((nt + 7) / 8) * 8;
   } else {

@@ -353,6 +353,7 @@ struct DArgs {
   int cin, cout, cpad;
   Dims in, out;
   FastDiv fo1, fo2;      // division by out.n[1], out.n[2]
+  int zc;                // 3D 2 -> 2 z-streaming form: planes per block
 };
 DArgs conv_args(const ConvLaunch& a, int* nblk);
 hipError_t launch_conv_batched(const ConvLaunch& proto, const BatchLaunch& b, hipStream_t s);
