@@ -172,7 +172,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
   // before any LDS store, so a block waits for one memory latency per batch
   // (small tiles, used on small grids, take the whole tile in one batch)
   {
-    constexpr int SB = (RPW * MT * NTW <= 2) ? 12 : 8;
+    constexpr int SB = (RPW * MT * NTW <= 2) ? (BG ? 16 : 12) : 8;
     const bool vec4 = (cin % 4) == 0;
     const int ng = cinp / 4;
     const int total = G::NODES * ng;
