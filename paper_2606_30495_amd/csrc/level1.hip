@@ -294,9 +294,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   // e box (STEP: halo 3 around the tile; RESID: halo 1); FIRST has e = 0
   constexpr int H = RESID ? 1 : 3;
   constexpr int EY = TY + 2 * H, EX = TX + 2 * H, NE = EY * EX;
-  // e planes held: STEP keeps k - 3 .. k + 1 (the output plane's e and the
-  // next plane being stored); RESID keeps k and k + 1
-  constexpr int NER = STEP ? 5 : 2;
+  // e planes held: k (being scattered) and k + 1 (being stored)
+  constexpr int NER = 2;
   // t box (halo 2) for STEP / FIRST; RESID computes t on the tile
   constexpr int TG = RESID ? 0 : 2;
   constexpr int TYt = TY + 2 * TG, TXt = TX + 2 * TG, NT = TYt * TXt;
@@ -304,9 +303,12 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
   constexpr int NO = TY * TX;
   constexpr int PE = (NE + NTH - 1) / NTH, PT = (NT + NTH - 1) / NTH;
   constexpr int PU = (NU + NTH - 1) / NTH, PO = (NO + NTH - 1) / NTH;
+  // t plane (FIRST: r plane) on the t box, u plane on the u box; STEP keeps
+  // two of each (one written, one read in the same iteration)
+  constexpr int NTU = STEP ? 2 : 1;
   __shared__ float2 se[FIRST ? 1 : NER * NE];
-  __shared__ float2 st[RESID ? 1 : NT];      // t plane (FIRST: r plane) on the t box
-  __shared__ float2 su[RESID ? 1 : NU];      // u plane on the u box
+  __shared__ float2 st[RESID ? 1 : NTU * NT];
+  __shared__ float2 su[RESID ? 1 : NTU * NU];
 
   const gptr<const float2> __restrict__ e = to_global<const float2>(A.e);
   const gptr<float2> __restrict__ eo = to_global<float2>(A.eo);
@@ -442,15 +444,13 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     ub[k] = (i < NU) ? (uy + 1) * TXt + (ux + 1) : TXt + 1;
     uoff[k] = poff(i < NU, y0 - 1 + uy, x0 - 1 + ux);
   }
-  // output tile: LDS base of tap (0, 0) in the u box, the point's e in the
-  // e box, grid offset
-  int ob[PO], oe[PO], ooff[PO];
+  // output tile: LDS base of tap (0, 0) in the u box, grid offset
+  int ob[PO], ooff[PO];
 #pragma unroll
   for (int k = 0; k < PO; ++k) {
     const int i = threadIdx.x + k * NTH;
     const int oy = i / TX, ox = i % TX;
     ob[k] = (i < NO) ? (oy + 1) * UX + (ox + 1) : UX + 1;
-    oe[k] = (i < NO) ? (oy + H) * EX + (ox + H) : 0;
     ooff[k] = poff(i < NO, y0 + oy, x0 + ox);
   }
   // e box (STEP / RESID): grid offset
@@ -554,46 +554,111 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     return;
   }
 
-  // STEP: plane k of e feeds t(k-1..k+1); t(k-1) feeds u(k-2..k); u(k-2)
-  // feeds out(k-3..k-1).  FIRST: plane k of r (= t) feeds u(k-1..k+1);
-  // u(k-1) feeds out(k-2..k).
-  constexpr int LAG = STEP ? 1 : 0;
-  const int k0 = zb - 2 - LAG, k1 = ze + 1 + LAG;
+  if constexpr (STEP) {
+    // One barrier per plane: the three scatters of an iteration are skewed
+    // by one plane each, and the t and u planes are double-buffered.
+    // Iteration k scatters e(k) into t and finishes t(k - 1) into st[k & 1];
+    // scatters t(k - 2) (st[(k - 1) & 1], finished one iteration earlier)
+    // into u and finishes u(k - 3) into su[k & 1]; scatters u(k - 4)
+    // (su[(k - 1) & 1]) into the output and finishes out(k - 5), whose own e
+    // is read from global memory.  Every LDS read of an iteration is of data
+    // written before its barrier, and every LDS buffer it writes was last
+    // read before that barrier.  A scatter is skipped when all the outputs
+    // it feeds lie outside the chunk's needs: t(zb - 2 .. ze + 1),
+    // u(zb - 1 .. ze), out(zb .. ze - 1).
+    const int k0 = zb - 3, k1 = ze + 4;
+    float2 evo[PO];                             // e of the output finished next
+    auto load_eo = [&](int z) {
+      const bool zok = zin(z);
+#pragma unroll
+      for (int j = 0; j < PO; ++j) evo[j] = ld(at(e, z), ooff[j], zok);
+    };
+    load_in(k0);
+    store_in(k0);
+    load_ra(k0 - 1);
+    load_s(k0 - 3);
+    load_eo(k0 - 5);
+    auto iter = [&](int k, auto rot) {
+      constexpr int R = decltype(rot)::value;
+      if (k + 1 <= ze + 2) load_in(k + 1);
+      __syncthreads();                          // e(k), t(k - 2), u(k - 4) published
+      // t(k - 1) = r - W e - a (.) (KA e), zero outside the grid
+      if (k <= ze + 2)
+        scatter(rot, integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
+                tw0, tw1, tk0, tk1, integral_constant<int, PT>());
+      {
+        float2* stw = st + (k & 1) * NT;
+        const bool qin = zin(k - 1);
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+          const int i = threadIdx.x + j * NTH;
+          if (i < NT)
+            stw[i] = (qin && toff[j] >= 0)
+                         ? make_float2(rv[j].x - tw0[R][j] - av[j].x * tk0[R][j],
+                                       rv[j].y - tw1[R][j] - av[j].y * tk1[R][j])
+                         : zero;
+        }
+        clear(tw0, rot); clear(tw1, rot); clear(tk0, rot); clear(tk1, rot);
+        load_ra(k);
+      }
+      // u(k - 3) = s (.) (KS * t), zero outside the grid
+      if (k >= zb && k <= ze + 3)
+        scatter(rot, integral_constant<bool, false>(), st + ((k - 1) & 1) * NT, TXt, &wg->KS[0][0][0],
+                ub, uc0, uc1, uc0, uc1, integral_constant<int, PU>());
+      {
+        float2* suw = su + (k & 1) * NU;
+        const bool pin = zin(k - 3);
+#pragma unroll
+        for (int j = 0; j < PU; ++j) {
+          const int i = threadIdx.x + j * NTH;
+          if (i < NU)
+            suw[i] = (pin && uoff[j] >= 0) ? make_float2(sv[j].x * uc0[R][j], sv[j].y * uc1[R][j]) : zero;
+        }
+        clear(uc0, rot); clear(uc1, rot);
+        load_s(k - 2);
+      }
+      // out(k - 5) = e + Wsm * u
+      if (k >= zb + 3)
+        scatter(rot, integral_constant<bool, false>(), su + ((k - 1) & 1) * NU, UX, &wg->Wsm[0][0][0],
+                ob, oc0, oc1, oc0, oc1, integral_constant<int, PO>());
+      {
+        const int z = k - 5;
+        if (z >= zb && z < ze) {
+          const auto oz = at(eo, z);
+#pragma unroll
+          for (int j = 0; j < PO; ++j)
+            if (ooff[j] >= 0)
+              gst(oz, (long long)(unsigned)ooff[j], make_float2(evo[j].x + oc0[R][j], evo[j].y + oc1[R][j]));
+        }
+        clear(oc0, rot); clear(oc1, rot);
+        load_eo(k - 4);
+      }
+      // e(k + 1) into the slot of e(k - 1), last read before the barrier
+      if (k + 1 <= ze + 2) store_in(k + 1);
+    };
+    for (int k = k0; k <= k1; k += 3) {
+      iter(k, R0);
+      if (k + 1 <= k1) iter(k + 1, R1);
+      if (k + 2 <= k1) iter(k + 2, R2);
+    }
+    return;
+  }
+
+  // FIRST (e = 0, t = r): plane k of r feeds u(k - 1 .. k + 1); u(k - 1)
+  // feeds out(k - 2 .. k).
+  const int k0 = zb - 2, k1 = ze + 1;
   load_in(k0);
   store_in(k0);
-  if constexpr (STEP) load_ra(k0 - 1);
-  load_s(k0 - 1 - LAG);
+  load_s(k0 - 1);
   auto iter = [&](int k, auto rot) {
     constexpr int R = decltype(rot)::value;
     if (k + 1 <= k1) load_in(k + 1);
-    __syncthreads();                            // input plane k published; su, st free
-    if constexpr (STEP) {
-      scatter(rot, integral_constant<bool, true>(), se + ring(k, NER) * NE, EX, &wg->WK[0][0][0], tb,
-              tw0, tw1, tk0, tk1, integral_constant<int, PT>());
-      // t(k - 1) = r - W e - a (.) (KA e), zero outside the grid
-      const bool qin = zin(k - 1);
-#pragma unroll
-      for (int j = 0; j < PT; ++j) {
-        const int i = threadIdx.x + j * NTH;
-        if (i < NT)
-          st[i] = (qin && toff[j] >= 0)
-                      ? make_float2(rv[j].x - tw0[R][j] - av[j].x * tk0[R][j],
-                                    rv[j].y - tw1[R][j] - av[j].y * tk1[R][j])
-                      : zero;
-      }
-      clear(tw0, rot); clear(tw1, rot); clear(tk0, rot); clear(tk1, rot);
-      if (k + 1 <= k1) load_ra(k);
-      __syncthreads();                          // t(k - 1) published
-    }
-    // u(p) = s (.) (KS * t), p = k - 1 - LAG, zero outside the grid.  The
-    // scatter of input plane q = k - LAG feeds u(q - 1 .. q + 1); the output
-    // phase reads u(zb - 1 .. ze) only, so the first planes of a chunk's
-    // march (STEP: two) are not scattered.
+    __syncthreads();                            // input plane k published; su free
+    // u(k - 1) = s (.) (KS * r), zero outside the grid
     {
-      if (k >= zb - 2 + LAG)
-        scatter(rot, integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0,
-                uc1, integral_constant<int, PU>());
-      const int p = k - 1 - LAG;
+      scatter(rot, integral_constant<bool, false>(), st, TXt, &wg->KS[0][0][0], ub, uc0, uc1, uc0, uc1,
+              integral_constant<int, PU>());
+      const int p = k - 1;
       const bool pin = zin(p);
 #pragma unroll
       for (int j = 0; j < PU; ++j) {
@@ -604,30 +669,25 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
       clear(uc0, rot); clear(uc1, rot);
       if (k + 1 <= k1) load_s(p + 1);
     }
-    __syncthreads();                            // u(p) published; st consumed
-    // out(z) = e + Wsm * u, z = k - 2 - LAG.  u(p) feeds out(p - 1 .. p + 1),
-    // so it is scattered only from p = zb - 1 on (the skipped planes' u and
-    // out are discarded, and slots enter the window cleared).
+    __syncthreads();                            // u(k - 1) published; the r plane consumed
+    // out(k - 2) = Wsm * u.  u(p) feeds out(p - 1 .. p + 1), so it is
+    // scattered only from p = zb - 1 on (the skipped planes' outputs are
+    // discarded, and slots enter the window cleared).
     {
-      if (k >= zb + LAG)
+      if (k >= zb)
         scatter(rot, integral_constant<bool, false>(), su, UX, &wg->Wsm[0][0][0], ob, oc0, oc1, oc0,
                 oc1, integral_constant<int, PO>());
-      const int z = k - 2 - LAG;
+      const int z = k - 2;
       if (z >= zb && z < ze) {
         const auto oz = at(eo, z);
 #pragma unroll
-        for (int j = 0; j < PO; ++j) {
-          if (ooff[j] >= 0) {
-            float2 ev = zero;
-            if (STEP) ev = se[ring(z, NER) * NE + oe[j]];
-            gst(oz, (long long)(unsigned)ooff[j], make_float2(ev.x + oc0[R][j], ev.y + oc1[R][j]));
-          }
-        }
+        for (int j = 0; j < PO; ++j)
+          if (ooff[j] >= 0)
+            gst(oz, (long long)(unsigned)ooff[j], make_float2(oc0[R][j], oc1[R][j]));
       }
       clear(oc0, rot); clear(oc1, rot);
-      // the next input plane: its slot held e(k - 4) (STEP), read by the
-      // previous iteration's output phase; FIRST's r plane was last read by
-      // this iteration's u phase, finished at the barrier above
+      // the next r plane: the current one was last read by this
+      // iteration's u phase, finished at the barrier above
       if (k + 1 <= k1) store_in(k + 1);
     }
   };
