@@ -21,13 +21,14 @@
 // (t = r - A e only, the input of the restriction).
 //
 // 3D uses a z-streaming form instead of cube tiles: a block owns a TY x TX
-// column and a chunk of ZC planes and walks it plane by plane, keeping the
-// last planes of e (halo 3 in y and x), t (halo 2) and u (halo 1) in LDS
-// rings.  Each plane of t and u is then computed once per block (a cube
+// column and a chunk of planes (sized at launch) and walks it plane by
+// plane, keeping planes of e (halo 3 in y and x), t (halo 2) and u (halo 1)
+// in LDS.  Each plane of t and u is then computed once per block (a cube
 // tile with a halo of 3 recomputes about four times the work), and only the
-// in-plane halos are shared with neighbouring blocks.  The tap loop runs
-// over dz at run time with the 9 in-plane taps unrolled, so at most one
-// plane's weights are live (the fully unrolled 27-tap form spills).
+// in-plane halos are shared with neighbouring blocks.  Every staged plane is
+// scattered once into the three output planes it feeds (see l1z_body); the
+// in-plane taps run at run time, so at most one tap's (or one tap row's)
+// weights are live (the fully unrolled 27-tap form spills).
 #include <algorithm>
 #include <type_traits>
 
