@@ -63,7 +63,15 @@ void mfma_pack_dims(int dim, int mode, int cin, int cout, int bf16, int* cinp, i
                     int* npairs, int* nsteps);
 // LDS of one block: the staged input tile plus the weight chunk, two chunk
 // buffers when the nsteps K-steps take more than one chunk.
-size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
+// Node stride (elements) of the staged input tile in LDS.  3D float32 at
+// C = 2 (the restriction from the finest level) stages only the two real
+// channels of a node: the K lanes of the padding channels 2 and 3 then read
+// the next node's values, which meet zero weights (the tile carries four
+// zero floats after its last node for them).
+__host__ __device__ inline int mfma_lds_stride(int dim, int bf16, int cin, int cinp) {
+  return (!bf16 && dim == 3 && cin == 2) ? 2 : cinp + (bf16 ? 8 : 1);
+}
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cin, int cinp, int epi,
                       int kchunk, int nsteps);
 // Whether a tile (mt, ntw, rpw) is instantiated for this dim / epilogue.
 bool mfma_tile_ok(int dim, int epi, int mt, int ntw, int rpw);

@@ -137,7 +137,7 @@ hipError_t launch_conv_mfma_batched(const MfmaConv& proto, const BatchLaunch& b,
   return dispatch(proto, &b, s);
 }
 
-size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cinp, int epi,
+size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int cin, int cinp, int epi,
                       int kchunk, int nsteps) {
   if (rpw == MFMAZ_RPW) return mfmaz_lds_bytes(epi);
   int TX, TY, TZ;
@@ -145,8 +145,8 @@ size_t mfma_lds_bytes(int dim, int bf16, int mode, int mt, int ntw, int rpw, int
   auto ext = [&](int t) { return mode == CONV_S1 ? t + 2 : (mode == CONV_S2 ? 2 * t + 1 : t + 1); };
   const size_t nodes = (size_t)ext(TX) * ext(TY) * (dim == 2 ? 1 : ext(TZ));
   const int es = bf16 ? 2 : 4, kv = bf16 ? 8 : 1, ks = kchunk;
-  const size_t stride = cinp + (bf16 ? 8 : 1);
-  const size_t a = ((nodes * stride * es + 15) / 16) * 16;
+  const size_t stride = mfma_lds_stride(dim, bf16, cin, cinp);
+  const size_t a = ((nodes * stride * es + 15) / 16) * 16 + (stride == 2 && !bf16 ? 16 : 0);
   // 3D float32 reads its B fragments from global memory: no weight chunk
   if (!bf16 && dim == 3) return a;
   const size_t b = (size_t)(epi == EPI_RESID ? 2 : 1) * 4 * ks * ntw * 16 * kv * es;

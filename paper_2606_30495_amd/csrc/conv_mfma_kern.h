@@ -76,7 +76,7 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
   constexpr int NACC = (EPI == EPI_RESID) ? 2 : 1;
   constexpr int ES = BF ? 2 : 4;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int stride = cinp + (BF ? 8 : 1);  // LDS node stride (elements)
+  const int stride = mfma_lds_stride(D, BF, cin, cinp);  // LDS node stride (elements)
   unsigned char* bsm = smem + (((size_t)G::NODES * stride * ES + 15) / 16) * 16;
   constexpr int BROW = NTW * 16 * KV;      // elements of one pair row in the chunk
   constexpr int V16 = BROW * ES / 16;      // 16-byte vectors per row
@@ -217,9 +217,11 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
         }
       }
     } else if (BG && cin == 2) {
-      // the C = 2 finest level (channels padded to 4, one group per node):
-      // one unconditional 8-byte load per node, zero-selected, stored with
-      // the two padding channels
+      // the C = 2 finest level (one group of 4 channels per node, 2 real):
+      // one unconditional 8-byte load per node, zero-selected, stored as the
+      // node's two floats (stride 2); the four floats after the last node
+      // are zero (read by the padding channels' K lanes of that node)
+      if (threadIdx.x < 4) reinterpret_cast<float*>(smem)[(size_t)G::NODES * 2 + threadIdx.x] = 0.f;
       const long long tile0 = (((long long)sz * IY + sy) * IX + sx) * 2;
       for (int base = threadIdx.x; base < total; base += 256 * SB) {
         float2 t[SB];
@@ -238,11 +240,8 @@ __device__ __forceinline__ void mconv_body(const MArgs& A, const int vblk, const
         for (int k = 0; k < SB; ++k) {
           const int node = base + k * 256;
           if (node >= total) continue;
-          float* sp = reinterpret_cast<float*>(smem) + (size_t)node * stride;
-          sp[0] = ok[k] ? t[k].x : 0.f;
-          sp[1] = ok[k] ? t[k].y : 0.f;
-          sp[2] = 0.f;
-          sp[3] = 0.f;
+          *reinterpret_cast<float2*>(reinterpret_cast<float*>(smem) + (size_t)node * 2) =
+              make_float2(ok[k] ? t[k].x : 0.f, ok[k] ? t[k].y : 0.f);
         }
       }
     } else
@@ -630,7 +629,7 @@ hipError_t run(const MfmaConv& a, const BatchLaunch* b, hipStream_t s) {
     return hipErrorInvalidValue;
   } else {
     const int nslices = a.ncols / (16 * NTW);
-    const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.rpw, a.cinp, a.epi, a.kchunk,
+    const size_t lds = mfma_lds_bytes(a.dim, a.bf16, a.mode, a.mt, a.ntw, a.rpw, a.cin, a.cinp, a.epi, a.kchunk,
                                       a.nsteps);
     if (b) {
       hipLaunchKernelGGL((mconv_kernel_batched<D, BF, MODE, EPI, MT, NTW, RPW>), dim3(b->total, nslices),

@@ -292,7 +292,7 @@ mcmg_status Ctx::plan_mfma() {
   // budget (a large staged tile) leaves less, the chunk takes the whole LDS.
   auto kchunk_for = [&](const MOp& op, const Tile& t) {
     auto bytes = [&](int kc) {
-      return mfma_lds_bytes(dim, bf, op.mode, t.mt, t.ntw, t.rpw, op.cinp, op.epi, kc, op.nsteps);
+      return mfma_lds_bytes(dim, bf, op.mode, t.mt, t.ntw, t.rpw, op.cin, op.cinp, op.epi, kc, op.nsteps);
     };
     auto cycles = [&](int kc) {
       return (double)kc * (op.epi == EPI_RESID ? 2 : 1) * t.rpw * t.mt * t.ntw * (bf ? 16.0 : 32.0);
@@ -317,7 +317,7 @@ mcmg_status Ctx::plan_mfma() {
           if (nt % ntw || !mfma_tile_ok(dim, op.epi, mt, ntw, rpw)) continue;
           const Tile t{mt, ntw, rpw};
           const int kc = kchunk_for(op, t);
-          if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cinp, op.epi, kc, op.nsteps) > lds_max) continue;
+          if (mfma_lds_bytes(dim, bf, op.mode, mt, ntw, rpw, op.cin, op.cinp, op.epi, kc, op.nsteps) > lds_max) continue;
           c.push_back(t);
         }
     // the z-marching form (3D float32 stride-1, 12 input channels)
