@@ -34,6 +34,40 @@ def test_short_kernel_names():
     assert profsum.short("__amd_rocclr_copyBuffer") == "__amd_rocclr_copyBuffer"
 
 
+def test_per_iteration_breakdown(tmp_path):
+    """profsum periter splits a kernel trace at a once-per-iteration marker
+    kernel: the kernels after one marker up to and including the next form
+    an iteration, keyed by name and grid size (blocks)."""
+    hdr = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Grid_Size_X", "Grid_Size_Y",
+           "Grid_Size_Z", "Workgroup_Size_X", "Workgroup_Size_Y", "Workgroup_Size_Z"]
+    rows, t = [], 0
+
+    def k(name, dur_us, blocks):                  # timestamps in ns
+        nonlocal t
+        rows.append([name, t, t + dur_us * 1000, blocks * 256, 1, 1, 256, 1, 1])
+        t += dur_us * 1000 + 5000
+
+    k("void warm(int)", 999, 1)                   # before the first marker: not counted
+    for it in range(3):
+        k("void mcmg::(anonymous namespace)::mark<1>(int)", 10, 4)
+        k("void a(int)", 100 + it, 8)
+        k("void a(int)", 50, 16)                  # same name, other grid: its own row
+        k("void b(int)", 20, 8)
+    k("void mcmg::(anonymous namespace)::mark<1>(int)", 10, 4)
+    path = tmp_path / "trace.csv"
+    _write_csv(str(path), hdr, rows)
+    out = profsum.per_iteration(str(path), "mark<1>", 3)
+    lines = {ln.split("|")[1].strip().strip("`") + "/" + ln.split("|")[2].strip(): ln
+             for ln in out.splitlines() if ln.startswith("| `")}
+    # us per iteration: a with 8 blocks ran 100, 101 and 102 us in the three
+    # iterations; with 16 blocks 50 us each; launches per iteration: 1
+    assert float(lines["a/8"].split("|")[3]) == pytest.approx(101.0)
+    assert float(lines["a/16"].split("|")[3]) == pytest.approx(50.0)
+    assert float(lines["b/8"].split("|")[5]) == pytest.approx(20.0)
+    assert float(lines["mark<1>/4"].split("|")[4]) == pytest.approx(1.0)
+    assert "warm" not in out
+
+
 def test_traffic_scales_by_the_copy_calibration(tmp_path):
     """Bytes per launch = FETCH_SIZE KiB x 1024 x (copy bytes / copy FETCH
     bytes) + the same for WRITE_SIZE; the JSON table records the source's
