@@ -336,6 +336,7 @@ def served_leg(nreq, rate, seed=3, scale="small"):
     done, i = {}, 0
     rid_of = {}
     t0 = time.perf_counter()
+    t_note = t0
     while len(done) < nreq:
         now = time.perf_counter() - t0
         while i < nreq and trace[i]["t"] <= now:
@@ -344,6 +345,9 @@ def served_leg(nreq, rate, seed=3, scale="small"):
         wait_ms = 20 if i >= nreq else max(0, min(20, int((trace[i]["t"] - now) * 1e3)))
         for c in srv.poll(64, wait_ms=wait_ms):
             done[rid_of[c["req_id"]]] = c
+        if time.perf_counter() - t_note > 20.0:     # long traces: a line every 20 s
+            t_note = time.perf_counter()
+            progress(f"served: {len(done)} of {nreq} requests finished")
     t_end = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
@@ -361,7 +365,11 @@ def served_leg(nreq, rate, seed=3, scale="small"):
     torch.cuda.synchronize()
     lat_p, ok_p, its_p, worst_p = [], 0, 0, 0.0
     t0 = time.perf_counter()
+    t_note = t0
     for k, r in enumerate(trace):
+        if time.perf_counter() - t_note > 20.0:
+            t_note = time.perf_counter()
+            progress(f"one at a time: request {k} of {nreq}")
         now = time.perf_counter() - t0
         if now < r["t"]:
             time.sleep(r["t"] - now)
