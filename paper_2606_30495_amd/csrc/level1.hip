@@ -381,7 +381,21 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
         }
       }
     };
-    if constexpr (PAIR) {
+    if constexpr (PAIR && NP <= 2) {
+      // few points per thread (the RESID form): a tap row's three taps'
+      // values are requested together, the weights still one tap at a time
+#pragma unroll 1
+      for (int dy = 0; dy < 3; ++dy) {
+        const int ro = (dy - 1) * pitch - 1;
+        float2 v[3][NP];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+          for (int k = 0; k < NP; ++k) v[dx][k] = P[base[k] + ro + dx];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) tap(v[dx], T + (3 * dy + dx) * TS);
+      }
+    } else if constexpr (PAIR) {
       // taps at run time, (dy, dx) row-major from (-1, -1): only one tap's
       // 24 weights are live
       int to = -pitch - 1, dx = 0;
