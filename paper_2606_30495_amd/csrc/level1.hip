@@ -381,9 +381,15 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
         }
       }
     };
-    if constexpr (PAIR && NP <= 2) {
-      // few points per thread (the RESID form): a tap row's three taps'
-      // values are requested together, the weights still one tap at a time
+    // A row of taps per iteration where its values fit the registers (one
+    // tensor: the u and output phases; two tensors with at most two points
+    // per thread: the RESID form): the row's three taps' values are
+    // requested together and waited for once, the weights of a row (36) or
+    // of one tap (24) are live.  The STEP t phase (two tensors, three points
+    // per thread) takes one tap per iteration.  Each accumulator takes the
+    // taps in row-major order either way.
+    constexpr bool ROWS = !PAIR || NP <= 2;
+    if constexpr (ROWS) {
 #pragma unroll 1
       for (int dy = 0; dy < 3; ++dy) {
         const int ro = (dy - 1) * pitch - 1;
@@ -395,9 +401,8 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) tap(v[dx], T + (3 * dy + dx) * TS);
       }
-    } else if constexpr (PAIR) {
-      // taps at run time, (dy, dx) row-major from (-1, -1): only one tap's
-      // 24 weights are live
+    } else {
+      // taps at run time, (dy, dx) row-major from (-1, -1)
       int to = -pitch - 1, dx = 0;
 #pragma unroll 1
       for (int t = 0; t < 9; ++t) {
@@ -411,21 +416,6 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
         } else {
           ++to;
         }
-      }
-    } else {
-      // one tap row per iteration: its three taps' values are requested
-      // together, so the row waits once for its loads (36 weights live);
-      // each accumulator still takes the taps in row-major order
-#pragma unroll 1
-      for (int dy = 0; dy < 3; ++dy) {
-        const int ro = (dy - 1) * pitch - 1;
-        float2 v[3][NP];
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-          for (int k = 0; k < NP; ++k) v[dx][k] = P[base[k] + ro + dx];
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) tap(v[dx], T + (3 * dy + dx) * TS);
       }
     }
   };
