@@ -449,13 +449,15 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     ub[k] = (i < NU) ? (uy + 1) * TXt + (ux + 1) : TXt + 1;
     uoff[k] = poff(i < NU, y0 - 1 + uy, x0 - 1 + ux);
   }
-  // output tile: LDS base of tap (0, 0) in the u box, grid offset
-  int ob[PO], ooff[PO];
+  // output tile: LDS base of tap (0, 0) in the u box, the point's e in the
+  // e box, grid offset
+  int ob[PO], oe[PO], ooff[PO];
 #pragma unroll
   for (int k = 0; k < PO; ++k) {
     const int i = threadIdx.x + k * NTH;
     const int oy = i / TX, ox = i % TX;
     ob[k] = (i < NO) ? (oy + 1) * UX + (ox + 1) : UX + 1;
+    oe[k] = (i < NO) ? (oy + H) * EX + (ox + H) : 0;
     ooff[k] = poff(i < NO, y0 + oy, x0 + ox);
   }
   // e box (STEP / RESID): grid offset
@@ -566,23 +568,24 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
     // scatters t(k - 2) (st[(k - 1) & 1], finished one iteration earlier)
     // into u and finishes u(k - 3) into su[k & 1]; scatters u(k - 4)
     // (su[(k - 1) & 1]) into the output and finishes out(k - 5), whose own e
-    // is read from global memory.  Every LDS read of an iteration is of data
-    // written before its barrier, and every LDS buffer it writes was last
-    // read before that barrier.  A scatter is skipped when all the outputs
+    // each thread copied from the LDS ring when its plane was there and
+    // carries in a five-deep register queue.  Every LDS read of an iteration
+    // is of data written before its barrier, and every LDS buffer it writes
+    // was last read before that barrier.  A scatter is skipped when all the outputs
     // it feeds lie outside the chunk's needs: t(zb - 2 .. ze + 1),
     // u(zb - 1 .. ze), out(zb .. ze - 1).
     const int k0 = zb - 3, k1 = ze + 4;
-    float2 evo[PO];                             // e of the output finished next
-    auto load_eo = [&](int z) {
-      const bool zok = zin(z);
+    // eq[q]: e at this thread's output points of plane k - 5 + q (entries of
+    // planes before the chunk's first output are never used)
+    float2 eq[5][PO];
 #pragma unroll
-      for (int j = 0; j < PO; ++j) evo[j] = ld(at(e, z), ooff[j], zok);
-    };
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int j = 0; j < PO; ++j) eq[q][j] = zero;
     load_in(k0);
     store_in(k0);
     load_ra(k0 - 1);
     load_s(k0 - 3);
-    load_eo(k0 - 5);
     auto iter = [&](int k, auto rot) {
       constexpr int R = decltype(rot)::value;
       if (k + 1 <= ze + 2) load_in(k + 1);
@@ -633,10 +636,16 @@ __device__ __forceinline__ void l1z_body(const L1Args& A, const L1ZWeights& wt, 
 #pragma unroll
           for (int j = 0; j < PO; ++j)
             if (ooff[j] >= 0)
-              gst(oz, (long long)(unsigned)ooff[j], make_float2(evo[j].x + oc0[R][j], evo[j].y + oc1[R][j]));
+              gst(oz, (long long)(unsigned)ooff[j], make_float2(eq[0][j].x + oc0[R][j], eq[0][j].y + oc1[R][j]));
         }
         clear(oc0, rot); clear(oc1, rot);
-        load_eo(k - 4);
+        // the queue moves on: e(k), in the ring this iteration, enters it
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int j = 0; j < PO; ++j) eq[q][j] = eq[q + 1][j];
+#pragma unroll
+        for (int j = 0; j < PO; ++j) eq[4][j] = se[ring(k, NER) * NE + oe[j]];
       }
       // e(k + 1) into the slot of e(k - 1), last read before the barrier
       if (k + 1 <= ze + 2) store_in(k + 1);
